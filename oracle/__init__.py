@@ -1,0 +1,159 @@
+"""CPU oracle for discrimination and millisecond histogramming.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package; the GPU library never does, and this
+package never imports the GPU library.  The arithmetic lives in plain C
+(``sinet_oracle.c``, single-threaded, built with gcc) and, for the learned
+index, in float64 numpy (``learned.py``).  See the C file's header for the
+definitions and the passages of the paper they follow.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sinet_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NO_INST = 0xFFFFFFFF
+
+EXTERNAL, EGRESS, INGRESS, INTERNAL = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, no vectorisation tricks)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        L.or_bitmask.argtypes = [u32, i32]
+        L.or_bitmask.restype = u32
+        L.or_match.argtypes = [u32, u32, i32]
+        L.or_match.restype = i32
+        L.or_lookup_scan.argtypes = [P, P, u64, u32, P]
+        L.or_lookup_scan.restype = i32
+        L.or_classify.argtypes = [P, P, P, u64, i32, P, P, u64, P, P, P]
+        L.or_classify.restype = i32
+        L.or_histogram.argtypes = [P, P, P, u64, u32, u32, u32, P, P, P, i32]
+        L.or_histogram.restype = i32
+        L.or_pipeline.argtypes = [P, P, P, u64, i32, P, P, P, P, u64, u32, u32, u32,
+                                  P, P, P, P, i32]
+        L.or_pipeline.restype = i32
+        L.or_endpoints.argtypes = [P, P, u64, P, P]
+        L.or_endpoints.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _table(base, plen, inst=None):
+    base = np.ascontiguousarray(base, dtype=np.uint32)
+    plen = np.ascontiguousarray(plen, dtype=np.uint8)
+    if inst is not None:
+        inst = np.ascontiguousarray(inst, dtype=np.uint32)
+    return base, plen, inst
+
+
+def bitmask(x: int, z: int) -> int:
+    return int(lib().or_bitmask(x & 0xFFFFFFFF, z))
+
+
+def match(a: int, base: int, z: int) -> bool:
+    return bool(lib().or_match(a & 0xFFFFFFFF, base & 0xFFFFFFFF, z))
+
+
+def lookup_scan(base, plen, a: int):
+    """(in, row) of one address by the linear Algorithm-1 scan."""
+    base, plen, _ = _table(base, plen)
+    row = ctypes.c_int64(-1)
+    hit = lib().or_lookup_scan(_p(base), _p(plen), base.shape[0], a & 0xFFFFFFFF,
+                               ctypes.byref(row))
+    return bool(hit), int(row.value)
+
+
+def classify(base, plen, src, dst, inst=None, mode: str = "hash", want_inst: bool = True):
+    """label[n] (uint8) and, if asked, src_inst/dst_inst[n] (uint32)."""
+    base, plen, inst = _table(base, plen, inst)
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    n = src.shape[0]
+    label = np.empty(n, np.uint8)
+    si = np.empty(n, np.uint32) if want_inst else None
+    di = np.empty(n, np.uint32) if want_inst else None
+    rc = lib().or_classify(_p(base), _p(plen), _p(inst), base.shape[0],
+                           0 if mode == "scan" else 1, _p(src), _p(dst), n,
+                           _p(label), _p(si), _p(di))
+    assert rc == 0
+    return (label, si, di) if want_inst else label
+
+
+def histogram(ts, nbytes, label, t0: int, width: int, n_bins: int, out=None):
+    """(count[4, n_bins], bytes[4, n_bins], dropped[4, 2]) as uint64.
+    With ``out`` given, adds into it (the accumulate mode)."""
+    ts = np.ascontiguousarray(ts, dtype=np.uint32)
+    nbytes = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    label = np.ascontiguousarray(label, dtype=np.uint8)
+    if out is None:
+        cnt = np.empty((4, n_bins), np.uint64)
+        byt = np.empty((4, n_bins), np.uint64)
+        drp = np.empty((4, 2), np.uint64)
+        acc = 0
+    else:
+        cnt, byt, drp = out
+        acc = 1
+    rc = lib().or_histogram(_p(ts), _p(nbytes), _p(label), ts.shape[0], t0, width, n_bins,
+                            _p(cnt), _p(byt), _p(drp), acc)
+    assert rc == 0
+    return cnt, byt, drp
+
+
+def pipeline(base, plen, ts, src, dst, nbytes, t0, width, n_bins, inst=None,
+             mode: str = "hash"):
+    """(label, count, bytes, dropped) of the fused definition."""
+    base, plen, inst = _table(base, plen, inst)
+    ts = np.ascontiguousarray(ts, dtype=np.uint32)
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    nbytes = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    n = ts.shape[0]
+    label = np.empty(n, np.uint8)
+    cnt = np.empty((4, n_bins), np.uint64)
+    byt = np.empty((4, n_bins), np.uint64)
+    drp = np.empty((4, 2), np.uint64)
+    rc = lib().or_pipeline(_p(base), _p(plen), _p(inst), base.shape[0],
+                           0 if mode == "scan" else 1, _p(ts), _p(src), _p(dst), _p(nbytes),
+                           n, t0, width, n_bins, _p(label), _p(cnt), _p(byt), _p(drp), 0)
+    assert rc == 0
+    return label, cnt, byt, drp
+
+
+def endpoints(base, plen):
+    """Sorted elementary-interval boundaries B[m] and owner[m] (LPM row + 1,
+    or 0 where no prefix covers the interval)."""
+    base, plen, _ = _table(base, plen)
+    P = base.shape[0]
+    B = np.empty(2 * P + 1, np.uint32)
+    own = np.empty(2 * P + 1, np.uint32)
+    m = lib().or_endpoints(_p(base), _p(plen), P, _p(B), _p(own))
+    assert m > 0
+    return B[:m].copy(), own[:m].copy()
