@@ -1,0 +1,260 @@
+/*
+ * sinet.h -- C ABI of libsinet: per-session ingress/egress discrimination of
+ * IPv4 sessions against a backbone prefix table, fused with an exact
+ * millisecond histogram, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Ando, Kadobayashi and Takakura, "Choice of
+ * Parallelism: Multi-GPU Driven Pipeline for Huge Academic Backbone Network"
+ * (arXiv 2106.12863):
+ *   - discrimination: Algorithm 1 and the section "Threads for traffic
+ *     direction discrimination with CIDR MATCH" (mask the address and the
+ *     CIDR base to Z bits, subtract, a zero result is a match);
+ *   - histogramming: the sections "Map", "Reduce", "Pairwise Reduction
+ *     Pattern with GPU" and "Merge Scatter Pattern with CPU" (key = time
+ *     bin, values <timestamp,count> and <timestamp,bytes>, 1-ms bins, merged
+ *     by an associative and commutative addition);
+ *   - batching of many uneven chunks through one work queue: sections
+ *     "Coordinated Batch Processing", "Work Queue" and "TASK DECOMPOSITION".
+ * The learned position model is not in the paper; it only changes how fast
+ * the exact interval is found.
+ *
+ * Conventions for every call:
+ *   - Column, label, institution and histogram buffers are DEVICE pointers
+ *     owned by the caller (hipMalloc or a framework tensor).  Prefix-table
+ *     inputs of sinet_table_create are HOST pointers, copied.
+ *   - Every call that takes a stream only enqueues work on it and returns;
+ *     the caller synchronises.  Argument errors are detected on the host
+ *     and returned before anything is enqueued.  A device fault surfaces as
+ *     SINET_ERR_DEVICE from a later call.
+ *   - n == 0 is a successful no-op (with accumulate == 0 the histogram is
+ *     still cleared).
+ *   - sinet_last_error() gives a thread-local description of the last
+ *     non-OK status.
+ *   - Tables and plans are library-owned; destroy them with their destroy
+ *     call.  A table is read-only after create/train and may be used by
+ *     concurrent calls on different streams.
+ */
+#ifndef SINET_H
+#define SINET_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SINET_OK = 0,
+    SINET_ERR_INVALID_ARG = 1,
+    SINET_ERR_OUT_OF_MEMORY = 2,
+    SINET_ERR_DEVICE = 3,
+    SINET_ERR_UNSUPPORTED = 4
+} sinet_status;
+
+/* Session label: bit 0 = source inside the table (the paper's "outgoing"
+ * mark of Algorithm 1), bit 1 = destination inside the table. */
+typedef enum {
+    SINET_EXTERNAL = 0,
+    SINET_EGRESS = 1,
+    SINET_INGRESS = 2,
+    SINET_INTERNAL = 3
+} sinet_label;
+
+/* How a table answers "which interval holds this address".  All kinds give
+ * identical results; they differ only in speed. */
+typedef enum {
+    SINET_LOOKUP_AUTO = 0,        /* scan for <= 64 prefixes, else bsearch   */
+    SINET_LOOKUP_SCAN = 1,        /* Algorithm 1 over every row (<= 1024)    */
+    SINET_LOOKUP_BSEARCH = 2,     /* binary search over sorted boundaries    */
+    SINET_LOOKUP_TRIE = 3,        /* 16-8-8 multibit trie                    */
+    SINET_LOOKUP_LEARNED_PLA = 4, /* piecewise-linear model + bounded search */
+    SINET_LOOKUP_LEARNED_MLP = 5  /* 1-16-1 ReLU MLP + bounded search        */
+} sinet_lookup;
+
+#define SINET_NO_INST 0xFFFFFFFFu
+#define SINET_MAX_PREFIXES (1u << 22)
+#define SINET_MLP_PARAMS 49
+
+typedef struct sinet_table sinet_table;           /* opaque, device-resident */
+typedef struct sinet_batch_plan sinet_batch_plan; /* opaque: queue + graph   */
+
+/* Session columns, structure of arrays, n sessions (device pointers).
+ * ts: capture time in ms (u32), src/dst: IPv4 host order, bytes: u64. */
+typedef struct {
+    const uint32_t* ts;
+    const uint32_t* src;
+    const uint32_t* dst;
+    const uint64_t* bytes;
+    uint64_t n;
+} sinet_columns;
+
+/* Histogram window: bin = floor((ts - t0_ms) / width_ms) for
+ * t0_ms <= ts and bin < n_bins; other sessions are counted in dropped. */
+typedef struct {
+    uint32_t t0_ms;
+    uint32_t width_ms;
+    uint32_t n_bins;
+} sinet_window;
+
+/* Histogram outputs (device): count[4][n_bins] and bytes[4][n_bins],
+ * label-major, unsigned 64-bit, exact modulo 2^64; dropped[4][2] =
+ * {count, bytes} per label, or NULL. */
+typedef struct {
+    uint64_t* count;
+    uint64_t* bytes;
+    uint64_t* dropped;
+} sinet_hist;
+
+typedef struct {
+    uint32_t kind;          /* sinet_lookup of the table                     */
+    uint64_t n_prefix;
+    uint64_t m;             /* number of interval boundaries                 */
+    uint64_t device_bytes;  /* device memory held by the table               */
+    uint32_t trained;       /* learned kinds: 1 after sinet_table_train      */
+    uint32_t max_err;       /* learned kinds: measured bound of the search   */
+    uint32_t segments;      /* PLA: number of segments                       */
+    uint64_t fallbacks;     /* learned kinds: bounded searches that fell back
+                               to the full search since create (synchronous
+                               read of a device counter)                     */
+} sinet_table_info_t;
+
+typedef struct {
+    uint32_t steps;         /* MLP: full-batch Adam steps (default 2000)     */
+    float lr;               /* MLP: Adam step size (default 1e-2)            */
+    const float* init;      /* MLP: host[49] start parameters, or NULL for
+                               hinges at k/16                                */
+    uint32_t segments;      /* PLA: segments, 1..65536 (default 256)         */
+} sinet_train_params;
+
+typedef struct {
+    float loss_first;       /* MLP: loss before the first step               */
+    float loss_last;        /* MLP: loss after the last step                 */
+    uint32_t max_err_untrained; /* MLP: bound with the start parameters      */
+    uint32_t max_err;       /* bound after training                          */
+    double train_ms;        /* device time of the training (hipEvents)       */
+} sinet_train_report;
+
+/* Autotuned launch parameters of the batched persistent kernel. */
+typedef struct {
+    uint32_t block;         /* threads per workgroup (64..1024, multiple of 64) */
+    uint32_t chunk;         /* sessions per work item (multiple of 4*block)  */
+    uint32_t grid;          /* persistent workgroups (0: one per slot)       */
+    uint32_t reserved;
+} sinet_tune;
+
+/* One independent stream of a batch: its columns, table, window and outputs. */
+typedef struct {
+    sinet_columns cols;
+    const sinet_table* table;
+    sinet_window win;
+    uint8_t* label;         /* device [n] or NULL                            */
+    sinet_hist hist;
+} sinet_stream;
+
+const char* sinet_status_string(sinet_status s);
+const char* sinet_last_error(void);
+const char* sinet_version(void);
+
+/* Build a table from n_prefix rows (HOST arrays, copied).  base: IPv4
+ * address, host bits allowed (they are masked off as Algorithm 1 masks the
+ * CIDR base); len: prefix length Z in 0..32; inst: institution id of the row
+ * (any value except SINET_NO_INST), or NULL for the row index.  The longest
+ * matching prefix gives the institution, equal lengths resolve to the lowest
+ * row.  Learned kinds need sinet_table_train before use.  Errors:
+ * INVALID_ARG (null pointer, len > 32, n_prefix == 0 or above
+ * SINET_MAX_PREFIXES, inst == SINET_NO_INST, SCAN above 1024 rows),
+ * OUT_OF_MEMORY.  Synchronous. */
+sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const uint32_t* inst,
+                                uint64_t n_prefix, sinet_lookup kind, hipStream_t stream,
+                                sinet_table** out);
+
+/* Fit the learned model of a LEARNED_PLA / LEARNED_MLP table on the GPU and
+ * measure its maximum position error over every interval.  params may be
+ * NULL (defaults); report may be NULL.  Synchronous. */
+sinet_status sinet_table_train(sinet_table* t, const sinet_train_params* params,
+                               hipStream_t stream, sinet_train_report* report);
+
+sinet_status sinet_table_info(const sinet_table* t, sinet_table_info_t* out);
+
+/* Save the learned model of a trained table to HOST arrays: MLP: params[49];
+ * PLA: knot[S], c[S], g[S] with S = info.segments <= cap.  Unused pointers
+ * may be NULL.  *max_err receives the search bound.  Synchronous. */
+sinet_status sinet_table_get_model(const sinet_table* t, float* params, uint32_t* knot, float* c,
+                                   float* g, uint32_t cap, uint32_t* max_err);
+
+/* Load a learned model (HOST arrays, copied), e.g. one saved by
+ * sinet_table_get_model: MLP: params[49]; PLA: segments rows of knot
+ * (ascending, knot[0] == 0), c and g (g >= 0).  max_err == 0xFFFFFFFF
+ * measures the bound on the GPU; any other value is used as given, and a
+ * bound that is too small only costs fallbacks (results stay exact).
+ * Synchronous. */
+sinet_status sinet_table_set_model(sinet_table* t, const float* params, const uint32_t* knot,
+                                   const float* c, const float* g, uint32_t segments,
+                                   uint32_t max_err);
+
+/* Copy the table's interval boundaries and owners (LPM row + 1, 0 = no
+ * prefix) to HOST arrays of capacity cap (>= m).  Synchronous. */
+sinet_status sinet_table_intervals(const sinet_table* t, uint32_t* B, uint32_t* owner,
+                                   uint64_t cap);
+
+sinet_status sinet_table_destroy(sinet_table* t);
+
+/* Interval index j (B[j] <= a < B[j+1]) of n addresses, by the table's own
+ * lookup method (device in, device out). */
+sinet_status sinet_table_position(const sinet_table* t, const uint32_t* addr, uint64_t n,
+                                  uint32_t* pos, hipStream_t stream);
+
+/* Discrimination (Algorithm 1 over the whole table, both endpoints):
+ * label[i] = in(src[i]) | in(dst[i]) << 1; src_inst/dst_inst[i] = institution
+ * of the longest matching prefix or SINET_NO_INST.  label, src_inst and
+ * dst_inst may each be NULL (not stored). */
+sinet_status sinet_discriminate(const sinet_table* t, const uint32_t* src, const uint32_t* dst,
+                                uint64_t n, uint8_t* label, uint32_t* src_inst,
+                                uint32_t* dst_inst, hipStream_t stream);
+
+/* Histogram of already labelled sessions (map to (label, bin), reduce by
+ * addition).  accumulate == 0: outputs are cleared first; 1: added to (the
+ * paper's merge of per-chunk results).  Errors: INVALID_ARG for null
+ * pointers, width_ms == 0, n_bins == 0. */
+sinet_status sinet_histogram(const uint32_t* ts, const uint64_t* bytes, const uint8_t* label,
+                             uint64_t n, const sinet_window* win, sinet_hist* out,
+                             int accumulate, hipStream_t stream);
+
+/* Discrimination fused with the histogram in one pass over the columns.
+ * label may be NULL (not stored). */
+sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols,
+                            const sinet_window* win, uint8_t* label, sinet_hist* out,
+                            int accumulate, hipStream_t stream);
+
+/* Forward and backward of the 1-16-1 MLP position model (device arrays):
+ * params[49] (w1[16], b1[16], w2[16], b2), inputs x[n], targets y[n];
+ * writes loss[1] = mean (f(x) - y)^2 and grad[49].  Float32, fixed-order
+ * reduction. */
+sinet_status sinet_mlp_loss_grad(const float* params, const float* x, const float* y,
+                                 uint64_t n, float* loss, float* grad, hipStream_t stream);
+
+/* Pick block/chunk/grid for a batch by timing candidates (results are
+ * identical for every candidate).  cache_path may be NULL; otherwise a JSON
+ * file read first and written after tuning.  Synchronous. */
+sinet_status sinet_autotune(const sinet_stream* streams, uint32_t n_streams,
+                            const char* cache_path, hipStream_t stream, sinet_tune* out);
+
+/* Prepare a batch: stream descriptors uploaded, clear + one persistent
+ * work-queue launch captured in a hipGraph.  tune may be NULL (defaults).
+ * The plan refers to the caller's buffers, which must outlive it. */
+sinet_status sinet_batch_plan_create(const sinet_stream* streams, uint32_t n_streams,
+                                     const sinet_tune* tune, hipStream_t stream,
+                                     sinet_batch_plan** out);
+
+/* Run a prepared batch (one graph launch): every stream's labels and
+ * histogram, cleared first, as if by sinet_pipeline per stream. */
+sinet_status sinet_batch_run(sinet_batch_plan* plan, hipStream_t stream);
+
+sinet_status sinet_batch_plan_destroy(sinet_batch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SINET_H */

@@ -136,3 +136,18 @@ def max_error(pred_fn, B: np.ndarray) -> float:
     hi[:-1] = B[1:] - 1
     hi[-1] = 0xFFFFFFFF
     return float(max(np.max(np.abs(pred_fn(lo) - j)), np.max(np.abs(pred_fn(hi) - j))))
+
+
+def mlp_grad_abs_sum(params, x, y):
+    """Per-parameter sum of |per-sample gradient terms| (the magnitude that a
+    float32 sum of those terms is accurate relative to)."""
+    w1, b1, w2, b2 = split(params)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = x.shape[0]
+    z = x[:, None] * w1[None, :] + b1[None, :]
+    h = np.maximum(z, 0.0)
+    r = h @ w2 + b2 - y
+    a = 2.0 * np.abs(r) / n
+    dz = (a[:, None] * np.abs(w2)[None, :]) * (z > 0.0)
+    return np.concatenate([dz.T @ np.abs(x), dz.sum(axis=0), h.T @ a, [a.sum()]])

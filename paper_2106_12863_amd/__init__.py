@@ -1,0 +1,376 @@
+"""Python binding of libsinet (session discrimination + millisecond histogram
+on MI355X).  Argument marshalling only: every step runs in the HIP library.
+
+Device buffers are torch tensors used purely as memory: uint32 columns live
+in int32 tensors, uint64 in int64 tensors, labels in uint8; the library
+reinterprets them as unsigned.  Calls are enqueued on torch's current stream.
+The library must be built (``__graft_entry__.build()``); importing this
+package without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsinet.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+EXTERNAL, EGRESS, INGRESS, INTERNAL = 0, 1, 2, 3
+NO_INST = 0xFFFFFFFF
+MLP_PARAMS = 49
+KINDS = {"auto": 0, "scan": 1, "bsearch": 2, "trie": 3, "pla": 4, "mlp": 5}
+KIND_NAMES = {v: k for k, v in KINDS.items()}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsinet is not built ({LIB_PATH} missing): run __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+P = ctypes.c_void_p
+U32, U64, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+
+
+class Columns(ctypes.Structure):
+    _fields_ = [("ts", P), ("src", P), ("dst", P), ("bytes", P), ("n", U64)]
+
+
+class Window(ctypes.Structure):
+    _fields_ = [("t0_ms", U32), ("width_ms", U32), ("n_bins", U32)]
+
+
+class Hist(ctypes.Structure):
+    _fields_ = [("count", P), ("bytes", P), ("dropped", P)]
+
+
+class TableInfo(ctypes.Structure):
+    _fields_ = [("kind", U32), ("n_prefix", U64), ("m", U64), ("device_bytes", U64),
+                ("trained", U32), ("max_err", U32), ("segments", U32), ("fallbacks", U64)]
+
+
+class TrainParams(ctypes.Structure):
+    _fields_ = [("steps", U32), ("lr", ctypes.c_float), ("init", P), ("segments", U32)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_float), ("loss_last", ctypes.c_float),
+                ("max_err_untrained", U32), ("max_err", U32), ("train_ms", ctypes.c_double)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("block", U32), ("chunk", U32), ("grid", U32), ("reserved", U32)]
+
+
+class Stream(ctypes.Structure):
+    _fields_ = [("cols", Columns), ("table", P), ("win", Window), ("label", P), ("hist", Hist)]
+
+
+def _sig(name, args, res=I32):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("sinet_status_string", [I32], ctypes.c_char_p)
+_sig("sinet_last_error", [], ctypes.c_char_p)
+_sig("sinet_version", [], ctypes.c_char_p)
+_sig("sinet_table_create", [P, P, P, U64, I32, P, ctypes.POINTER(P)])
+_sig("sinet_table_train", [P, ctypes.POINTER(TrainParams), P, ctypes.POINTER(TrainReport)])
+_sig("sinet_table_info", [P, ctypes.POINTER(TableInfo)])
+_sig("sinet_table_intervals", [P, P, P, U64])
+_sig("sinet_table_get_model", [P, P, P, P, P, U32, P])
+_sig("sinet_table_set_model", [P, P, P, P, P, U32, U32])
+_sig("sinet_table_destroy", [P])
+_sig("sinet_table_position", [P, P, U64, P, P])
+_sig("sinet_discriminate", [P, P, P, U64, P, P, P, P])
+_sig("sinet_histogram", [P, P, P, U64, ctypes.POINTER(Window), ctypes.POINTER(Hist), I32, P])
+_sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
+                        ctypes.POINTER(Hist), I32, P])
+_sig("sinet_mlp_loss_grad", [P, P, P, U64, P, P, P])
+_sig("sinet_autotune", [P, U32, ctypes.c_char_p, P, ctypes.POINTER(Tune)])
+_sig("sinet_batch_plan_create", [P, U32, ctypes.POINTER(Tune), P, ctypes.POINTER(P)])
+_sig("sinet_batch_run", [P, P])
+_sig("sinet_batch_plan_destroy", [P])
+
+
+class SinetError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.sinet_last_error().decode()
+        super().__init__(f"{where}: {_lib.sinet_status_string(status).decode()} ({msg})")
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise SinetError(rc, where)
+
+
+def version() -> str:
+    return _lib.sinet_version().decode()
+
+
+def lib():
+    return _lib
+
+
+def _stream(device=None):
+    import torch
+    return P(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else P(t.data_ptr())
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("device tensors must be CUDA (HIP) and contiguous")
+
+
+class Table:
+    """Device-resident prefix table (library-owned)."""
+
+    def __init__(self, base, plen, inst=None, kind: str = "auto"):
+        base = np.ascontiguousarray(base, dtype=np.uint32)
+        plen = np.ascontiguousarray(plen, dtype=np.uint8)
+        self._inst = None if inst is None else np.ascontiguousarray(inst, dtype=np.uint32)
+        out = P()
+        rc = _lib.sinet_table_create(base.ctypes.data_as(P), plen.ctypes.data_as(P),
+                                     None if self._inst is None else self._inst.ctypes.data_as(P),
+                                     base.shape[0], KINDS[kind], _stream(), ctypes.byref(out))
+        _check(rc, "sinet_table_create")
+        self.handle = out
+        self.n_prefix = base.shape[0]
+
+    def train(self, steps: int = 0, lr: float = 0.0, init: Optional[Sequence[float]] = None,
+              segments: int = 0) -> TrainReport:
+        prm = TrainParams()
+        prm.steps, prm.lr, prm.segments = steps, lr, segments
+        buf = None
+        if init is not None:
+            buf = np.ascontiguousarray(init, dtype=np.float32)
+            prm.init = buf.ctypes.data_as(P)
+        rep = TrainReport()
+        _check(_lib.sinet_table_train(self.handle, ctypes.byref(prm), _stream(), ctypes.byref(rep)),
+               "sinet_table_train")
+        return rep
+
+    def get_model(self):
+        """Saved model: ("mlp", params[49], max_err) or ("pla", (knot, c, g), max_err)."""
+        inf = self.info()
+        err = ctypes.c_uint32()
+        if KIND_NAMES[inf.kind] == "mlp":
+            prm = np.empty(MLP_PARAMS, np.float32)
+            _check(_lib.sinet_table_get_model(self.handle, prm.ctypes.data_as(P), None, None, None,
+                                              0, ctypes.byref(err)), "sinet_table_get_model")
+            return "mlp", prm, err.value
+        S = inf.segments
+        knot, c, g = np.empty(S, np.uint32), np.empty(S, np.float32), np.empty(S, np.float32)
+        _check(_lib.sinet_table_get_model(self.handle, None, knot.ctypes.data_as(P),
+                                          c.ctypes.data_as(P), g.ctypes.data_as(P), S,
+                                          ctypes.byref(err)), "sinet_table_get_model")
+        return "pla", (knot, c, g), err.value
+
+    def set_model(self, params=None, pla=None, max_err: Optional[int] = None):
+        """Load a model; max_err None measures the bound on the GPU."""
+        e = 0xFFFFFFFF if max_err is None else int(max_err)
+        if params is not None:
+            prm = np.ascontiguousarray(params, dtype=np.float32)
+            _check(_lib.sinet_table_set_model(self.handle, prm.ctypes.data_as(P), None, None, None,
+                                              0, e), "sinet_table_set_model")
+        else:
+            knot = np.ascontiguousarray(pla[0], dtype=np.uint32)
+            c = np.ascontiguousarray(pla[1], dtype=np.float32)
+            g = np.ascontiguousarray(pla[2], dtype=np.float32)
+            _check(_lib.sinet_table_set_model(self.handle, None, knot.ctypes.data_as(P),
+                                              c.ctypes.data_as(P), g.ctypes.data_as(P),
+                                              knot.shape[0], e), "sinet_table_set_model")
+
+    def info(self) -> TableInfo:
+        inf = TableInfo()
+        _check(_lib.sinet_table_info(self.handle, ctypes.byref(inf)), "sinet_table_info")
+        return inf
+
+    @property
+    def kind(self) -> str:
+        return KIND_NAMES[self.info().kind]
+
+    def intervals(self):
+        m = self.info().m
+        B = np.empty(m, np.uint32)
+        own = np.empty(m, np.uint32)
+        _check(_lib.sinet_table_intervals(self.handle, B.ctypes.data_as(P), own.ctypes.data_as(P), m),
+               "sinet_table_intervals")
+        return B, own
+
+    def position(self, addr, out=None):
+        import torch
+        _dev_check(addr)
+        if out is None:
+            out = torch.empty_like(addr, dtype=torch.int32)
+        _check(_lib.sinet_table_position(self.handle, _ptr(addr), addr.shape[0], _ptr(out),
+                                         _stream(addr.device)), "sinet_table_position")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.sinet_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def discriminate(table: Table, src, dst, label=True, src_inst=False, dst_inst=False):
+    """Labels (uint8) and optional institution ids (int32 storage of uint32)."""
+    import torch
+    _dev_check(src, dst)
+    n = src.shape[0]
+    dev = src.device
+    lab = torch.empty(n, dtype=torch.uint8, device=dev) if label is True else (label or None)
+    si = torch.empty(n, dtype=torch.int32, device=dev) if src_inst is True else (src_inst or None)
+    di = torch.empty(n, dtype=torch.int32, device=dev) if dst_inst is True else (dst_inst or None)
+    _check(_lib.sinet_discriminate(table.handle, _ptr(src), _ptr(dst), n, _ptr(lab), _ptr(si),
+                                   _ptr(di), _stream(dev)), "sinet_discriminate")
+    return lab, si, di
+
+
+def new_hist(n_bins: int, device="cuda"):
+    import torch
+    return (torch.empty((4, n_bins), dtype=torch.int64, device=device),
+            torch.empty((4, n_bins), dtype=torch.int64, device=device),
+            torch.empty((4, 2), dtype=torch.int64, device=device))
+
+
+def _hist_struct(out):
+    h = Hist()
+    h.count, h.bytes = _ptr(out[0]), _ptr(out[1])
+    h.dropped = _ptr(out[2]) if len(out) > 2 and out[2] is not None else None
+    return h
+
+
+def histogram(ts, nbytes, label, t0: int, width: int, n_bins: int, out=None,
+              accumulate: bool = False):
+    _dev_check(ts, nbytes, label)
+    out = new_hist(n_bins, ts.device) if out is None else out
+    w = Window(t0, width, n_bins)
+    h = _hist_struct(out)
+    _check(_lib.sinet_histogram(_ptr(ts), _ptr(nbytes), _ptr(label), ts.shape[0], ctypes.byref(w),
+                                ctypes.byref(h), int(accumulate), _stream(ts.device)),
+           "sinet_histogram")
+    return out
+
+
+def pipeline(table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: int, label=True,
+             out=None, accumulate: bool = False):
+    """Fused discrimination + histogram.  Returns (label or None, (count, bytes, dropped))."""
+    import torch
+    _dev_check(ts, src, dst, nbytes)
+    n = ts.shape[0]
+    lab = torch.empty(n, dtype=torch.uint8, device=ts.device) if label is True else (label or None)
+    out = new_hist(n_bins, ts.device) if out is None else out
+    c = Columns(_ptr(ts), _ptr(src), _ptr(dst), _ptr(nbytes), n)
+    w = Window(t0, width, n_bins)
+    h = _hist_struct(out)
+    _check(_lib.sinet_pipeline(table.handle, ctypes.byref(c), ctypes.byref(w), _ptr(lab),
+                               ctypes.byref(h), int(accumulate), _stream(ts.device)),
+           "sinet_pipeline")
+    return lab, out
+
+
+def mlp_loss_grad(params, x, y):
+    """(loss[1], grad[49]) float32 device tensors."""
+    import torch
+    _dev_check(params, x, y)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    _check(_lib.sinet_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(y), x.shape[0], _ptr(loss),
+                                    _ptr(grad), _stream(x.device)), "sinet_mlp_loss_grad")
+    return loss, grad
+
+
+class BatchStream:
+    """One stream of a batch: columns, table, window, outputs (device tensors)."""
+
+    def __init__(self, table: Table, ts, src, dst, nbytes, t0, width, n_bins, label=None, out=None):
+        self.table, self.ts, self.src, self.dst, self.nbytes = table, ts, src, dst, nbytes
+        self.t0, self.width, self.n_bins = t0, width, n_bins
+        self.label = label
+        self.out = out
+
+    def struct(self) -> Stream:
+        s = Stream()
+        s.cols = Columns(_ptr(self.ts), _ptr(self.src), _ptr(self.dst), _ptr(self.nbytes),
+                         self.ts.shape[0])
+        s.table = self.table.handle
+        s.win = Window(self.t0, self.width, self.n_bins)
+        s.label = _ptr(self.label)
+        s.hist = _hist_struct(self.out)
+        return s
+
+
+def _streams_array(streams):
+    arr = (Stream * len(streams))()
+    for i, s in enumerate(streams):
+        arr[i] = s.struct()
+    return arr
+
+
+def autotune(streams, cache_path: Optional[str] = None) -> Tune:
+    arr = _streams_array(streams)
+    t = Tune()
+    _check(_lib.sinet_autotune(arr, len(streams), None if cache_path is None else cache_path.encode(),
+                               _stream(), ctypes.byref(t)), "sinet_autotune")
+    return t
+
+
+class BatchPlan:
+    def __init__(self, streams, tune: Optional[Tune] = None):
+        self.streams = list(streams)   # keeps the buffers alive
+        arr = _streams_array(self.streams)
+        out = P()
+        _check(_lib.sinet_batch_plan_create(arr, len(self.streams),
+                                            None if tune is None else ctypes.byref(tune),
+                                            _stream(), ctypes.byref(out)),
+               "sinet_batch_plan_create")
+        self.handle = out
+
+    def run(self):
+        _check(_lib.sinet_batch_run(self.handle, _stream()), "sinet_batch_run")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.sinet_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# host <-> device helpers for uint32/uint64 data held in signed tensors
+def to_device_u32(a, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to(device)
+
+
+def to_device_u64(a, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(device)
+
+
+def to_host_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def to_host_u64(t):
+    return t.cpu().numpy().view(np.uint64)

@@ -178,12 +178,10 @@ class Workload:
 # ----------------------------------------------------------------------------
 # Session columns for arbitrary index sets (host)
 # ----------------------------------------------------------------------------
-def _ts(wl: Workload, idx: np.ndarray) -> np.ndarray:
-    r = draw(wl.keys()[0], idx) >> U64(32)
-    if wl.ts_mode == TS_UNIFORM:
-        t = _mulhi32(r, wl.ts_span).astype(np.int64)
-        return (t + wl.t_origin).astype(np.uint32)
-    i = idx.astype(np.int64)
+def ts_base(wl: Workload, idx: np.ndarray) -> np.ndarray:
+    """Un-jittered time of session i (non-decreasing in i), before the origin
+    offset: the diurnal inverse CDF at (i + 1/2)/n, or a uniform rate."""
+    i = np.asarray(idx).astype(np.int64)
     if wl.ts_mode == TS_DIURNAL:
         q = diurnal_table(wl.ts_span)
         num = (2 * i + 1) * QTAB_K
@@ -192,9 +190,31 @@ def _ts(wl: Workload, idx: np.ndarray) -> np.ndarray:
         frac = num % den
         qk = q[k].astype(np.int64)
         dq = q[k + 1].astype(np.int64) - qk
-        base = (qk + (dq * frac) // den) >> QTAB_FRAC_BITS
-    else:  # TS_STRATIFIED: uniform rate over [0, W)
-        base = ((2 * i + 1) * wl.ts_span) // (2 * wl.n)
+        return (qk + (dq * frac) // den) >> QTAB_FRAC_BITS
+    return ((2 * i + 1) * wl.ts_span) // (2 * wl.n)   # TS_STRATIFIED: uniform rate
+
+
+def index_range_for_time(wl: Workload, t_lo: int, t_hi: int):
+    """Smallest index range [i0, i1) holding every session whose un-jittered
+    time lies in [t_lo, t_hi] (bisection on the monotone base)."""
+    def first_at_least(t):
+        lo, hi = 0, wl.n
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if int(ts_base(wl, np.array([mid]))[0]) >= t:
+                hi = mid
+            else:
+                lo = mid + 1
+        return lo
+    return first_at_least(t_lo), first_at_least(t_hi + 1)
+
+
+def _ts(wl: Workload, idx: np.ndarray) -> np.ndarray:
+    r = draw(wl.keys()[0], idx) >> U64(32)
+    if wl.ts_mode == TS_UNIFORM:
+        t = _mulhi32(r, wl.ts_span).astype(np.int64)
+        return (t + wl.t_origin).astype(np.uint32)
+    base = ts_base(wl, idx)
     J = wl.jitter
     j = _mulhi32(r, 2 * J + 1).astype(np.int64) - J
     x = base + j
