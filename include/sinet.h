@@ -72,6 +72,10 @@ typedef enum {
     SINET_LOOKUP_LEARNED_MLP = 5  /* 1-16-1 ReLU MLP + bounded search        */
 } sinet_lookup;
 
+/* OR-ed into the kind argument of sinet_table_create: do not build the
+ * in/out index, so label-only queries also run the kind's own search. */
+#define SINET_TABLE_NO_INOUT_INDEX 0x100u
+
 #define SINET_NO_INST 0xFFFFFFFFu
 #define SINET_MAX_PREFIXES (1u << 22)
 #define SINET_MLP_PARAMS 49
@@ -108,6 +112,7 @@ typedef struct {
 
 typedef struct {
     uint32_t kind;          /* sinet_lookup of the table                     */
+    uint32_t inout_index;   /* 1: label-only queries use the in/out index    */
     uint64_t n_prefix;
     uint64_t m;             /* number of interval boundaries                 */
     uint64_t device_bytes;  /* device memory held by the table               */
@@ -124,7 +129,11 @@ typedef struct {
     float lr;               /* MLP: Adam step size (default 1e-2)            */
     const float* init;      /* MLP: host[49] start parameters, or NULL for
                                hinges at k/16                                */
-    uint32_t segments;      /* PLA: segments, 1..65536 (default 256)         */
+    uint32_t segments;      /* PLA: equal-count least-squares segments, 1..65535;
+                               0 = error-bounded segmentation (target_err)   */
+    uint32_t target_err;    /* PLA with segments == 0: greedy segmentation with
+                               at most this error in boundaries (default 8;
+                               raised until the segments fit in LDS)          */
 } sinet_train_params;
 
 typedef struct {
@@ -156,7 +165,13 @@ const char* sinet_status_string(sinet_status s);
 const char* sinet_last_error(void);
 const char* sinet_version(void);
 
-/* Build a table from n_prefix rows (HOST arrays, copied).  base: IPv4
+/* Build a table from n_prefix rows (HOST arrays, copied).  Besides the
+ * structure of its lookup kind, every table except SCAN gets an in/out
+ * index when it fits in LDS (a 2-bit state per /16 block plus the sorted
+ * 16-bit offsets of the boundaries of the union of all prefixes inside the
+ * /16 blocks that such a boundary cuts); label-only queries are answered from
+ * it, the kind's search serves institution ids and positions.  kind may be
+ * OR-ed with SINET_TABLE_NO_INOUT_INDEX.  base: IPv4
  * address, host bits allowed (they are masked off as Algorithm 1 masks the
  * CIDR base); len: prefix length Z in 0..32; inst: institution id of the row
  * (any value except SINET_NO_INST), or NULL for the row index.  The longest

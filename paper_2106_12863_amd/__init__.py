@@ -24,6 +24,7 @@ NO_INST = 0xFFFFFFFF
 MLP_PARAMS = 49
 KINDS = {"auto": 0, "scan": 1, "bsearch": 2, "trie": 3, "pla": 4, "mlp": 5}
 KIND_NAMES = {v: k for k, v in KINDS.items()}
+NO_INOUT_INDEX = 0x100
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libsinet is not built ({LIB_PATH} missing): run __graft_entry__.build()")
@@ -46,12 +47,14 @@ class Hist(ctypes.Structure):
 
 
 class TableInfo(ctypes.Structure):
-    _fields_ = [("kind", U32), ("n_prefix", U64), ("m", U64), ("device_bytes", U64),
+    _fields_ = [("kind", U32), ("inout_index", U32), ("n_prefix", U64), ("m", U64),
+                ("device_bytes", U64),
                 ("trained", U32), ("max_err", U32), ("segments", U32), ("fallbacks", U64)]
 
 
 class TrainParams(ctypes.Structure):
-    _fields_ = [("steps", U32), ("lr", ctypes.c_float), ("init", P), ("segments", U32)]
+    _fields_ = [("steps", U32), ("lr", ctypes.c_float), ("init", P), ("segments", U32),
+                ("target_err", U32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -134,22 +137,24 @@ def _dev_check(*ts):
 class Table:
     """Device-resident prefix table (library-owned)."""
 
-    def __init__(self, base, plen, inst=None, kind: str = "auto"):
+    def __init__(self, base, plen, inst=None, kind: str = "auto", inout_index: bool = True):
         base = np.ascontiguousarray(base, dtype=np.uint32)
         plen = np.ascontiguousarray(plen, dtype=np.uint8)
         self._inst = None if inst is None else np.ascontiguousarray(inst, dtype=np.uint32)
         out = P()
         rc = _lib.sinet_table_create(base.ctypes.data_as(P), plen.ctypes.data_as(P),
                                      None if self._inst is None else self._inst.ctypes.data_as(P),
-                                     base.shape[0], KINDS[kind], _stream(), ctypes.byref(out))
+                                     base.shape[0],
+                                     KINDS[kind] | (0 if inout_index else NO_INOUT_INDEX),
+                                     _stream(), ctypes.byref(out))
         _check(rc, "sinet_table_create")
         self.handle = out
         self.n_prefix = base.shape[0]
 
     def train(self, steps: int = 0, lr: float = 0.0, init: Optional[Sequence[float]] = None,
-              segments: int = 0) -> TrainReport:
+              segments: int = 0, target_err: int = 0) -> TrainReport:
         prm = TrainParams()
-        prm.steps, prm.lr, prm.segments = steps, lr, segments
+        prm.steps, prm.lr, prm.segments, prm.target_err = steps, lr, segments, target_err
         buf = None
         if init is not None:
             buf = np.ascontiguousarray(init, dtype=np.float32)
@@ -228,15 +233,26 @@ class Table:
             pass
 
 
+def _opt_out(arg, n, dtype, device):
+    """True: allocate; False/None: not stored; a tensor: written in place."""
+    import torch
+    if arg is True:
+        return torch.empty(n, dtype=dtype, device=device)
+    if arg is None or arg is False:
+        return None
+    _dev_check(arg)
+    return arg
+
+
 def discriminate(table: Table, src, dst, label=True, src_inst=False, dst_inst=False):
     """Labels (uint8) and optional institution ids (int32 storage of uint32)."""
     import torch
     _dev_check(src, dst)
     n = src.shape[0]
     dev = src.device
-    lab = torch.empty(n, dtype=torch.uint8, device=dev) if label is True else (label or None)
-    si = torch.empty(n, dtype=torch.int32, device=dev) if src_inst is True else (src_inst or None)
-    di = torch.empty(n, dtype=torch.int32, device=dev) if dst_inst is True else (dst_inst or None)
+    lab = _opt_out(label, n, torch.uint8, dev)
+    si = _opt_out(src_inst, n, torch.int32, dev)
+    di = _opt_out(dst_inst, n, torch.int32, dev)
     _check(_lib.sinet_discriminate(table.handle, _ptr(src), _ptr(dst), n, _ptr(lab), _ptr(si),
                                    _ptr(di), _stream(dev)), "sinet_discriminate")
     return lab, si, di
@@ -274,7 +290,7 @@ def pipeline(table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: in
     import torch
     _dev_check(ts, src, dst, nbytes)
     n = ts.shape[0]
-    lab = torch.empty(n, dtype=torch.uint8, device=ts.device) if label is True else (label or None)
+    lab = _opt_out(label, n, torch.uint8, ts.device)
     out = new_hist(n_bins, ts.device) if out is None else out
     c = Columns(_ptr(ts), _ptr(src), _ptr(dst), _ptr(nbytes), n)
     w = Window(t0, width, n_bins)

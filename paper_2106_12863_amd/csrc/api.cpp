@@ -28,7 +28,8 @@ sinet_status check_hip(hipError_t e, const char* what) {
 
 static constexpr uint32_t kLdsTopMax = 16384;        // sampled boundaries kept in LDS
 static constexpr uint32_t kLdsMemberMaxWords = 16384; // membership bits kept in LDS
-static constexpr uint32_t kMaxSegments = 65536;
+static constexpr uint32_t kLdsReserveWords = 3072;    // static LDS of the pass kernels
+static constexpr uint32_t kMaxSegments = 65535;       // PLA segment index fits 16 bits
 
 static uint32_t prefix_mask(uint32_t z) {
     return z == 0 ? 0u : (z >= 32 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (32 - z)));
@@ -110,6 +111,75 @@ static void build_trie(const std::vector<uint32_t>& B, std::vector<uint32_t>& tr
     }
 }
 
+// In/out index over the union of all prefixes (label-only queries).  The
+// union's boundaries U are the points where membership changes.  A /16
+// block no boundary of U cuts is wholly in or out (2-bit state 1 / 0);
+// a cut block (state 2) gets an ordinal r, its membership at the block start
+// and the sorted low 16 bits of the boundaries inside it: an address is in
+// iff the start state differs from the parity of the boundaries <= its low
+// 16 bits.  Layout (32-bit words): filter[4096] | rank[4096] u16 (cut blocks
+// before each filter word) | start[M + 1] u16 | start bits[M] | list[T] u16.
+// Returns false when the ordinals or offsets would not fit 16 bits.
+static bool build_inout(const std::vector<uint32_t>& B, const std::vector<uint32_t>& owner,
+                        std::vector<uint32_t>& io, DevTable& d) {
+    std::vector<uint32_t> U;
+    bool prev = false;
+    for (size_t j = 0; j < B.size(); ++j) {
+        const bool in = owner[j] != 0;
+        if (in != prev) U.push_back(B[j]);
+        prev = in;
+    }
+    std::vector<uint32_t> filt(kFilterWords, 0);
+    std::vector<uint32_t> rank(kFilterWords, 0), start, sbit, list;
+    size_t u = 0;
+    bool state = false;
+    uint32_t mixed = 0;
+    for (uint64_t k = 0; k < 65536; ++k) {
+        if ((k & 15) == 0) rank[k >> 4] = mixed;
+        const uint64_t base = k << 16;
+        while (u < U.size() && U[u] == base) {
+            state = !state;
+            ++u;
+        }
+        const bool s0 = state;
+        const size_t u0 = u;
+        while (u < U.size() && ((uint64_t)U[u] >> 16) == k) {
+            state = !state;
+            ++u;
+        }
+        uint32_t st = s0 ? 1u : 0u;
+        if (u != u0) {
+            st = 2;
+            start.push_back((uint32_t)list.size());
+            sbit.push_back(s0 ? 1u : 0u);
+            for (size_t v = u0; v < u; ++v) list.push_back(U[v] & 0xFFFFu);
+            ++mixed;
+        }
+        filt[k >> 4] |= st << ((k & 15) * 2);
+    }
+    start.push_back((uint32_t)list.size());
+    if (mixed + 1 > 65535 || list.size() > 65535) return false;
+    auto pack16 = [](const std::vector<uint32_t>& v, std::vector<uint32_t>& out) {
+        for (size_t i = 0; i < v.size(); i += 2)
+            out.push_back((v[i] & 0xFFFFu) | (i + 1 < v.size() ? (v[i + 1] & 0xFFFFu) << 16 : 0u));
+    };
+    io.assign(filt.begin(), filt.end());
+    d.io_rank = (uint32_t)io.size();
+    pack16(rank, io);
+    d.io_start = (uint32_t)io.size();
+    pack16(start, io);
+    d.io_sbit = (uint32_t)io.size();
+    for (uint32_t r = 0; r < mixed; r += 32) {
+        uint32_t w = 0;
+        for (uint32_t b = 0; b < 32 && r + b < mixed; ++b) w |= sbit[r + b] << b;
+        io.push_back(w);
+    }
+    d.io_list = (uint32_t)io.size();
+    pack16(list, io);
+    d.io_words = (uint32_t)io.size();
+    return true;
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static uint32_t lds_bytes_for(const DevTable& t, uint32_t kind) {
@@ -118,11 +188,30 @@ static uint32_t lds_bytes_for(const DevTable& t, uint32_t kind) {
         case SINET_LOOKUP_SCAN: return 12u * t.n_prefix;
         case SINET_LOOKUP_BSEARCH: words = t.n_top; break;
         case SINET_LOOKUP_TRIE: break;
-        case SINET_LOOKUP_LEARNED_PLA: words = 3 * t.segments; break;
+        case SINET_LOOKUP_LEARNED_PLA: words = 3 * t.segments + radix_words(t.radix_bits); break;
         case SINET_LOOKUP_LEARNED_MLP: words = SINET_MLP_PARAMS; break;
         default: break;
     }
-    return 4u * (words + t.lds_member_words);
+    return 4u * (words + t.lds_member_words + (t.filter_lds ? kFilterWords : 0u));
+}
+
+// LDS words a PLA of S segments needs next to the filter and member bits.
+static uint32_t pla_lds_words(const DevTable& t, uint32_t S) {
+    return 3 * S + radix_words(t.radix_bits) + t.lds_member_words + (t.filter_lds ? kFilterWords : 0u);
+}
+
+// 2-bit state of every /16 block: 0 no prefix covers any of it, 1 one interval
+// covers all of it and is inside the table, 2 a boundary cuts it.
+static void build_filter(const std::vector<uint32_t>& B, const std::vector<uint32_t>& owner,
+                         std::vector<uint32_t>& filter) {
+    filter.assign(kFilterWords, 0);
+    for (uint64_t k = 0; k < 65536; ++k) {
+        const uint32_t lo = (uint32_t)(k << 16), hi = lo | 0xFFFFu;
+        const uint32_t j0 = (uint32_t)(std::upper_bound(B.begin(), B.end(), lo) - B.begin()) - 1;
+        const uint32_t j1 = (uint32_t)(std::upper_bound(B.begin(), B.end(), hi) - B.begin()) - 1;
+        const uint32_t st = j0 != j1 ? 2u : (owner[j0] ? 1u : 0u);
+        filter[k >> 4] |= st << ((k & 15) * 2);
+    }
 }
 
 static sinet_status check_device(const sinet_table* t) {
@@ -138,6 +227,17 @@ static sinet_status check_usable(const sinet_table* t) {
     if ((t->kind == SINET_LOOKUP_LEARNED_PLA || t->kind == SINET_LOOKUP_LEARNED_MLP) && !t->trained)
         return fail(SINET_ERR_INVALID_ARG, "learned table used before sinet_table_train");
     return check_device(t);
+}
+
+// The device view a pass uses: label-only passes of a table with an in/out
+// index run the index kind (LDS holds the index alone).
+static DevTable label_view(const sinet_table* t, bool label_only) {
+    DevTable d = t->dev;
+    if (label_only && d.io) {
+        d.kind = kInoutKind;
+        d.lds_bytes = 4u * d.io_words;
+    }
+    return d;
 }
 
 static sinet_status check_window(const sinet_window* w) {
@@ -184,6 +284,8 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     if (!base || !len) return fail(SINET_ERR_INVALID_ARG, "base or len is NULL");
     if (n_prefix == 0) return fail(SINET_ERR_INVALID_ARG, "n_prefix is 0");
     if (n_prefix > SINET_MAX_PREFIXES) return fail(SINET_ERR_INVALID_ARG, "too many prefixes");
+    const bool want_io = (kind & SINET_TABLE_NO_INOUT_INDEX) == 0;
+    kind = (sinet_lookup)(kind & ~SINET_TABLE_NO_INOUT_INDEX);
     if (kind == SINET_LOOKUP_AUTO) kind = n_prefix <= 64 ? SINET_LOOKUP_SCAN : SINET_LOOKUP_BSEARCH;
     if (kind < SINET_LOOKUP_SCAN || kind > SINET_LOOKUP_LEARNED_MLP)
         return fail(SINET_ERR_INVALID_ARG, "unknown lookup kind");
@@ -209,20 +311,37 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     std::vector<uint32_t> member(mw, 0);
     for (uint32_t j = 0; j < m; ++j)
         if (t->owner[j]) member[j >> 5] |= 1u << (j & 31);
-    // LDS plan: membership bits first (every interval kind reads them), then
-    // as many sampled boundaries as the per-workgroup LDS limit leaves room for.
+    // LDS plan: the /16 filter and the membership bits first (every interval
+    // kind reads them), then as many sampled boundaries as the per-workgroup
+    // LDS limit leaves room for.
     int lds_limit = 65536;
     if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, t->device) !=
             hipSuccess || lds_limit <= 0)
         lds_limit = 65536;
     const uint32_t lds_words = (uint32_t)std::min(lds_limit, 160 * 1024) / 4;
-    const uint32_t member_lds = (mw <= kLdsMemberMaxWords && mw <= lds_words / 2) ? mw : 0;
-    const uint32_t top_cap = std::min<uint32_t>(kLdsTopMax, lds_words - member_lds - 3 * 1024);
+    const bool interval_kind = kind != SINET_LOOKUP_SCAN;
+    const uint32_t filter_lds = interval_kind && lds_words >= kFilterWords + 8192 + kLdsReserveWords ? 1u : 0u;
+    const uint32_t fw = filter_lds ? kFilterWords : 0u;
+    const uint32_t member_lds =
+        (mw <= kLdsMemberMaxWords && fw + mw + 1024 + kLdsReserveWords <= lds_words) ? mw : 0;
+    const uint32_t top_cap = std::min<uint32_t>(kLdsTopMax, lds_words - fw - member_lds - kLdsReserveWords);
     uint32_t top_log2 = 0;
     while (((uint64_t)m + (1ull << top_log2) - 1) >> top_log2 > top_cap) ++top_log2;
     const uint32_t n_top = (uint32_t)(((uint64_t)m + (1ull << top_log2) - 1) >> top_log2);
     std::vector<uint32_t> top(n_top);
     for (uint32_t i = 0; i < n_top; ++i) top[i] = t->B[(size_t)i << top_log2];
+    // boundaries padded with 0xFFFFFFFF to whole leaf blocks of 2^top_log2
+    const uint64_t m_pad = (uint64_t)n_top << top_log2;
+    std::vector<uint32_t> Bpad(t->B);
+    Bpad.resize(m_pad, 0xFFFFFFFFu);
+    std::vector<uint32_t> filter;
+    if (interval_kind) build_filter(t->B, t->owner, filter);
+    std::vector<uint32_t> io;
+    DevTable iod;
+    memset(&iod, 0, sizeof(iod));
+    bool io_ok = interval_kind && want_io && build_inout(t->B, t->owner, io, iod) &&
+                 io.size() + kLdsReserveWords <= lds_words;
+    if (!io_ok) io.clear();
     std::vector<uint32_t> trie;
     if (kind == SINET_LOOKUP_TRIE) build_trie(t->B, trie);
     const bool learned = kind == SINET_LOOKUP_LEARNED_PLA || kind == SINET_LOOKUP_LEARNED_MLP;
@@ -231,11 +350,13 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     // one arena
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    const size_t oB = take(4ull * m), oOwn = take(4ull * m), oMem = take(4ull * mw),
+    const uint32_t rw = learned ? radix_words(kPlaRadixBits) : 0;
+    const size_t oB = take(4ull * m_pad), oOwn = take(4ull * m), oMem = take(4ull * mw),
                  oInst = take(4 * P), oCb = take(4 * P), oMk = take(4 * P), oLn = take(4 * P),
                  oTop = take(4ull * n_top), oTrie = take(4 * trie.size()),
                  oKnot = take(4ull * smax), oC = take(4ull * smax), oG = take(4ull * smax),
-                 oMlp = take(4 * SINET_MLP_PARAMS), oFb = take(8);
+                 oMlp = take(4 * SINET_MLP_PARAMS), oFb = take(8), oRadix = take(4ull * rw),
+                 oFilter = take(4ull * filter.size()), oIo = take(4ull * io.size());
     void* arena = nullptr;
     hipError_t e = hipMalloc(&arena, off);
     if (e != hipSuccess) {
@@ -250,7 +371,9 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
         return hipMemcpyAsync(a + o, src, bytes, hipMemcpyHostToDevice, stream);
     };
     hipError_t r = hipSuccess;
-    if (r == hipSuccess) r = up(oB, t->B.data(), 4ull * m);
+    if (r == hipSuccess) r = up(oB, Bpad.data(), 4ull * m_pad);
+    if (r == hipSuccess) r = up(oFilter, filter.data(), 4ull * filter.size());
+    if (r == hipSuccess) r = up(oIo, io.data(), 4ull * io.size());
     if (r == hipSuccess) r = up(oOwn, t->owner.data(), 4ull * m);
     if (r == hipSuccess) r = up(oMem, member.data(), 4ull * mw);
     if (r == hipSuccess) r = up(oInst, id.data(), 4 * P);
@@ -287,6 +410,18 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     d.pla_c = (const float*)(a + oC);
     d.pla_g = (const float*)(a + oG);
     d.mlp = (const float*)(a + oMlp);
+    d.radix = (const uint32_t*)(a + oRadix);
+    d.radix_bits = kPlaRadixBits;
+    d.filter = filter.empty() ? nullptr : (const uint32_t*)(a + oFilter);
+    d.filter_lds = filter.empty() ? 0u : filter_lds;
+    if (io_ok) {
+        d.io = (const uint32_t*)(a + oIo);
+        d.io_words = iod.io_words;
+        d.io_rank = iod.io_rank;
+        d.io_start = iod.io_start;
+        d.io_sbit = iod.io_sbit;
+        d.io_list = iod.io_list;
+    }
     d.m_f = (float)m;
     d.fallbacks = (unsigned long long*)(a + oFb);
     d.lds_member_words = member_lds;
@@ -304,11 +439,13 @@ sinet_status sinet_table_train(sinet_table* t, const sinet_train_params* params,
     sinet_train_report rep;
     memset(&rep, 0, sizeof(rep));
     if (t->kind == SINET_LOOKUP_LEARNED_PLA) {
-        uint32_t S = params && params->segments ? params->segments : 256;
-        if (S > kMaxSegments) return fail(SINET_ERR_INVALID_ARG, "segments above 65536");
-        if (3 * S + t->dev.lds_member_words > t->lds_words)
-            return fail(SINET_ERR_INVALID_ARG, "segments do not fit in LDS next to the member bits");
-        st = train_pla(t, S, stream, &rep);
+        const uint32_t S = params ? params->segments : 0;
+        const uint32_t E = params ? params->target_err : 0;
+        if (S > kMaxSegments) return fail(SINET_ERR_INVALID_ARG, "segments above 65535");
+        if (S && pla_lds_words(t->dev, S) + kLdsReserveWords > t->lds_words)
+            return fail(SINET_ERR_INVALID_ARG, "segments do not fit in LDS next to the filter and member bits");
+        const uint32_t smax = (t->lds_words - kLdsReserveWords - pla_lds_words(t->dev, 0)) / 3;
+        st = train_pla(t, S, E, std::min(smax, kMaxSegments), stream, &rep);
     } else if (t->kind == SINET_LOOKUP_LEARNED_MLP) {
         st = train_mlp(t, params, stream, &rep);
     } else {
@@ -325,6 +462,7 @@ sinet_status sinet_table_info(const sinet_table* t, sinet_table_info_t* out) {
     if (!t || !out) return fail(SINET_ERR_INVALID_ARG, "NULL argument");
     memset(out, 0, sizeof(*out));
     out->kind = t->kind;
+    out->inout_index = t->dev.io ? 1u : 0u;
     out->n_prefix = t->n_prefix;
     out->m = t->dev.m;
     out->device_bytes = t->arena_bytes;
@@ -371,8 +509,8 @@ sinet_status sinet_table_set_model(sinet_table* t, const float* params, const ui
         if (!knot || !c || !g) return fail(SINET_ERR_INVALID_ARG, "PLA arrays are NULL");
         if (segments == 0 || segments > kMaxSegments || segments > t->dev.m)
             return fail(SINET_ERR_INVALID_ARG, "bad segment count");
-        if (3 * segments + t->dev.lds_member_words > t->lds_words)
-            return fail(SINET_ERR_INVALID_ARG, "segments do not fit in LDS next to the member bits");
+        if (pla_lds_words(t->dev, segments) + kLdsReserveWords > t->lds_words)
+            return fail(SINET_ERR_INVALID_ARG, "segments do not fit in LDS next to the filter and member bits");
         if (knot[0] != 0) return fail(SINET_ERR_INVALID_ARG, "knot[0] must be 0");
         for (uint32_t s = 0; s < segments; ++s) {
             if (s && knot[s] <= knot[s - 1]) return fail(SINET_ERR_INVALID_ARG, "knots not ascending");
@@ -383,6 +521,8 @@ sinet_status sinet_table_set_model(sinet_table* t, const float* params, const ui
         if (e == hipSuccess) e = hipMemcpy((void*)t->dev.pla_g, g, 4ull * segments, hipMemcpyHostToDevice);
         t->dev.segments = segments;
         t->segments = segments;
+        std::vector<uint32_t> kn(knot, knot + segments);
+        if (e == hipSuccess) e = upload_radix(t, kn);
     } else {
         return fail(SINET_ERR_INVALID_ARG, "table kind is not learned");
     }
@@ -441,7 +581,7 @@ sinet_status sinet_discriminate(const sinet_table* t, const uint32_t* src, const
     if (!label && !src_inst && !dst_inst) return SINET_OK;
     PassParams p;
     memset(&p, 0, sizeof(p));
-    p.t = t->dev;
+    p.t = label_view(t, !src_inst && !dst_inst);
     p.src = src;
     p.dst = dst;
     p.label_out = label;
@@ -458,8 +598,9 @@ sinet_status sinet_histogram(const uint32_t* ts, const uint64_t* bytes, const ui
     if (st != SINET_OK) return st;
     if (!out || !out->count || !out->bytes) return fail(SINET_ERR_INVALID_ARG, "histogram output is NULL");
     if (n && (!ts || !bytes || !label)) return fail(SINET_ERR_INVALID_ARG, "column is NULL");
-    if (!accumulate) {
-        st = clear_hist(win, out, stream);
+    if (!accumulate && (n == 0 || out->dropped)) {
+        st = n == 0 ? clear_hist(win, out, stream)
+                    : launch_zero((unsigned long long*)out->dropped, 8, stream);
         if (st != SINET_OK) return st;
     }
     if (n == 0) return SINET_OK;
@@ -476,7 +617,7 @@ sinet_status sinet_histogram(const uint32_t* ts, const uint64_t* bytes, const ui
     p.width = win->width_ms;
     p.n_bins = win->n_bins;
     p.magic = div_magic(win->width_ms);
-    return launch_pass(p, PASS_HIST | PASS_LABEL_IN, stream);
+    return run_hist(p, PASS_HIST | PASS_LABEL_IN, accumulate, stream);
 }
 
 sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols, const sinet_window* win,
@@ -489,14 +630,15 @@ sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols, con
     if (!out || !out->count || !out->bytes) return fail(SINET_ERR_INVALID_ARG, "histogram output is NULL");
     if (cols->n && (!cols->ts || !cols->src || !cols->dst || !cols->bytes))
         return fail(SINET_ERR_INVALID_ARG, "column is NULL");
-    if (!accumulate) {
-        st = clear_hist(win, out, stream);
+    if (!accumulate && (cols->n == 0 || out->dropped)) {
+        st = cols->n == 0 ? clear_hist(win, out, stream)
+                          : launch_zero((unsigned long long*)out->dropped, 8, stream);
         if (st != SINET_OK) return st;
     }
     if (cols->n == 0) return SINET_OK;
     PassParams p;
     memset(&p, 0, sizeof(p));
-    p.t = t->dev;
+    p.t = label_view(t, true);
     p.ts = cols->ts;
     p.src = cols->src;
     p.dst = cols->dst;
@@ -510,7 +652,7 @@ sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols, con
     p.width = win->width_ms;
     p.n_bins = win->n_bins;
     p.magic = div_magic(win->width_ms);
-    return launch_pass(p, PASS_LABEL | PASS_HIST, stream);
+    return run_hist(p, PASS_LABEL | PASS_HIST, accumulate, stream);
 }
 
 sinet_status sinet_mlp_loss_grad(const float* params, const float* x, const float* y, uint64_t n,

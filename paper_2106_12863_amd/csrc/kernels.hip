@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string.h>
+
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -43,39 +45,32 @@ enum KernelKind : uint32_t {
     KK_TRIE = SINET_LOOKUP_TRIE,
     KK_PLA = SINET_LOOKUP_LEARNED_PLA,
     KK_MLP = SINET_LOOKUP_LEARNED_MLP,
-    KK_LABEL_IN = 100  // histogram of given labels
+    KK_INOUT = kInoutKind,  // label-only lookups through the in/out index
+    KK_LABEL_IN = 100       // histogram of given labels
 };
 
 constexpr int kXcds = 8;
 constexpr int kMaxBlock = 1024;
+constexpr int kStage1Block = kChunk / 4;  // 4 sessions per lane
+constexpr int kStage2Block = 256;
+constexpr int kSegBatch = kStage2Block;    // segments staged per stage-2 round
+constexpr int kRecUnroll = 8;              // independent record loads per stage-2 lane
+constexpr uint32_t kSmallMax = 1u << 19;  // byte counts stored inline in a record
+constexpr uint64_t kMaxPiece = 1ull << 31;  // sessions per partitioned pass (32-bit slots)
 
 // ---------------------------------------------------------------------------
 // searches
+//
+// A lane looks up several addresses at once (its four sessions' sources and
+// destinations).  Every search below advances all of them in lockstep, one
+// probe level at a time, so a lane keeps that many independent LDS or global
+// loads in flight instead of waiting out one dependent chain per address.
 // ---------------------------------------------------------------------------
-// Learned forms: the model's rounded prediction p is within max_err of the
-// true interval for every boundary key; search [p - e, p + e] and confirm the
-// bracket B[j] <= a < B[j+1], else fall back to the full search.
-__device__ __forceinline__ uint32_t bounded_search(const DevTable& t, uint32_t a, int p) {
-    int e = (int)t.max_err;
-    int lo = p - e;
-    int hi = p + e;
-    lo = lo < 0 ? 0 : lo;
-    hi = hi > (int)t.m - 1 ? (int)t.m - 1 : hi;
-    bool ok = t.B[lo] <= a;
-    uint32_t j = 0;
-    if (ok) {
-        j = (uint32_t)lo + upper_last(t.B + lo, (uint32_t)(hi - lo + 1), a);
-        if (j == (uint32_t)hi && (uint32_t)hi + 1 < t.m && t.B[hi + 1] <= a) ok = false;
-    }
-    if (!ok) {
-        atomicAdd(t.fallbacks, 1ull);
-        j = upper_last(t.B, t.m, a);
-    }
-    return j;
-}
 
 // Per-workgroup LDS view of the table.
 struct LdsView {
+    const uint32_t* io;      // in/out index
+    const uint32_t* filter;  // 2-bit state of every /16 block (interval kinds)
     const uint32_t* top;     // BSEARCH
     const uint32_t* member;  // all interval kinds (or global)
     const uint32_t* cb;      // SCAN
@@ -84,29 +79,136 @@ struct LdsView {
     const uint32_t* knot;    // PLA
     const float* c;
     const float* g;
+    const uint32_t* radix;   // PLA: first segment of each radix bucket (u16 pairs)
     const float* w;          // MLP
 };
 
-// Interval index of a (all kinds but SCAN).
-template <uint32_t KIND>
-__device__ __forceinline__ uint32_t interval_of(const DevTable& t, const LdsView& v, uint32_t a) {
-    if constexpr (KIND == KK_BSEARCH) {
-        uint32_t i = upper_last(v.top, t.n_top, a);
-        if (t.top_log2 == 0) return i;
-        uint32_t lo = i << t.top_log2;
-        uint32_t cnt = min(1u << t.top_log2, t.m - lo);
-        return lo + upper_last(t.B + lo, cnt, a);
-    } else if constexpr (KIND == KK_TRIE) {
-        uint32_t e = t.trie[a >> 16];
-        if (!(e >> 31)) {
-            e = t.trie[65536u + e * 256u + ((a >> 8) & 255u)];
-            if (!(e >> 31)) e = t.trie[65536u + e * 256u + (a & 255u)];
+// For each q: the last arr[i] <= a[q] among arr[0..n), given arr[0] <= a[q].
+template <int N>
+__device__ __forceinline__ void upper_last_n(const uint32_t* arr, uint32_t n, const uint32_t* a,
+                                             uint32_t* lo) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) lo[q] = 0;
+    while (n > 1) {
+        const uint32_t half = n >> 1;
+#pragma unroll
+        for (int q = 0; q < N; ++q) lo[q] = (arr[lo[q] + half] <= a[q]) ? lo[q] + half : lo[q];
+        n -= half;
+    }
+}
+
+// Same over per-address windows arr[base[q] .. base[q] + n) (absolute result).
+template <int N>
+__device__ __forceinline__ void upper_last_based(const uint32_t* arr, uint32_t n, const uint32_t* a,
+                                                 uint32_t* lo) {
+    while (n > 1) {
+        const uint32_t half = n >> 1;
+#pragma unroll
+        for (int q = 0; q < N; ++q) lo[q] = (arr[lo[q] + half] <= a[q]) ? lo[q] + half : lo[q];
+        n -= half;
+    }
+}
+
+__device__ __forceinline__ uint32_t radix_entry(const uint32_t* radix, uint32_t i) {
+    return (radix[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
+}
+
+// Learned forms: the model's rounded prediction p is within max_err of the
+// true interval for every boundary key; search a window of W = 2 e + 1
+// boundaries around p (shifted inside [0, m)) and confirm the bracket
+// B[j] <= a < B[j+1], else fall back to the full search.
+template <int N>
+__device__ __forceinline__ void bounded_search_n(const DevTable& t, const uint32_t* a, const int* p,
+                                                 uint32_t* j, uint32_t need) {
+    const uint32_t W = min(2 * t.max_err + 1, t.m);
+    uint32_t lo[N];
+    bool ok[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        int l = p[q] - (int)t.max_err;
+        l = l < 0 ? 0 : l;
+        l = (uint32_t)l + W > t.m ? (int)(t.m - W) : l;
+        lo[q] = (uint32_t)l;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) ok[q] = (need >> q) & 1u ? t.B[lo[q]] <= a[q] : true;
+    uint32_t first[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) first[q] = lo[q];
+    uint32_t n = W;
+    while (n > 1) {
+        const uint32_t half = n >> 1;
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if ((need >> q) & 1u) lo[q] = (t.B[lo[q] + half] <= a[q]) ? lo[q] + half : lo[q];
+        n -= half;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        if (!((need >> q) & 1u)) continue;
+        const uint32_t last = first[q] + W - 1;
+        if (ok[q] && lo[q] == last && last + 1 < t.m && t.B[last + 1] <= a[q]) ok[q] = false;
+        j[q] = lo[q];
+        if (!ok[q]) {
+            atomicAdd(t.fallbacks, 1ull);
+            j[q] = upper_last(t.B, t.m, a[q]);
         }
-        return e & 0x7FFFFFFFu;
+    }
+}
+
+// Interval index of each address (all kinds but SCAN).  Addresses whose bit
+// in `need` is clear are skipped (their j is left unspecified); skipped lanes
+// issue no memory requests.
+template <uint32_t KIND, int N>
+__device__ __forceinline__ void intervals(const DevTable& t, const LdsView& v, const uint32_t* a,
+                                          uint32_t* j, uint32_t need = 0xFFFFFFFFu) {
+    if constexpr (KIND == KK_BSEARCH) {
+        upper_last_n<N>(v.top, t.n_top, a, j);
+        if (t.top_log2 == 0) return;
+        // the boundary array is padded with 0xFFFFFFFF to whole leaf blocks
+#pragma unroll
+        for (int q = 0; q < N; ++q) j[q] <<= t.top_log2;
+        uint32_t n = 1u << t.top_log2;
+        while (n > 1) {
+            const uint32_t half = n >> 1;
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                if ((need >> q) & 1u) j[q] = (t.B[j[q] + half] <= a[q]) ? j[q] + half : j[q];
+            n -= half;
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) j[q] = min(j[q], t.m - 1);
+    } else if constexpr (KIND == KK_TRIE) {
+        uint32_t e[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) e[q] = (need >> q) & 1u ? t.trie[a[q] >> 16] : 0x80000000u;
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (!(e[q] >> 31)) e[q] = t.trie[65536u + e[q] * 256u + ((a[q] >> 8) & 255u)];
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (!(e[q] >> 31)) e[q] = t.trie[65536u + e[q] * 256u + (a[q] & 255u)];
+#pragma unroll
+        for (int q = 0; q < N; ++q) j[q] = e[q] & 0x7FFFFFFFu;
     } else if constexpr (KIND == KK_PLA) {
-        return bounded_search(t, a, clamp_pos(pla_predict(v.knot, v.c, v.g, t.segments, a), t.m));
+        int p[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            p[q] = 0;
+            if (!((need >> q) & 1u)) continue;
+            // radix bucket -> candidate segments -> last knot <= a
+            const uint32_t r = a[q] >> (32 - t.radix_bits);
+            const uint32_t s0 = radix_entry(v.radix, r), s1 = radix_entry(v.radix, r + 1);
+            const uint32_t s = s0 + upper_last(v.knot + s0, s1 - s0 + 1, a[q]);
+            p[q] = clamp_pos(pla_eval(v.knot[s], v.c[s], v.g[s], a[q]), t.m);
+        }
+        bounded_search_n<N>(t, a, p, j, need);
     } else {  // KK_MLP
-        return bounded_search(t, a, clamp_pos(mlp_predict(v.w, t.m_f, a), t.m));
+        int p[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            p[q] = (need >> q) & 1u ? clamp_pos(mlp_predict(v.w, t.m_f, a[q]), t.m) : 0;
+        bounded_search_n<N>(t, a, p, j, need);
     }
 }
 
@@ -124,28 +226,84 @@ __device__ __forceinline__ uint32_t scan_owner(const DevTable& t, const LdsView&
     return best;
 }
 
-struct Lookup {
-    uint32_t in;     // 0/1
-    uint32_t code;   // owner code (row + 1 or 0), valid when want_code
-};
+// In/out mark (and, when want_code, the owner code row + 1 or 0) of each
+// address.  Label-only lookups first consult the /16 filter: a block that no
+// boundary cuts is entirely in or entirely out, which answers most addresses
+// from LDS; only addresses in cut blocks run the table's search.
+__device__ __forceinline__ uint32_t u16_at(const uint32_t* w, uint32_t i) {
+    return (w[i >> 1] >> ((i & 1u) * 16)) & 0xFFFFu;
+}
 
-template <uint32_t KIND>
-__device__ __forceinline__ Lookup lookup(const DevTable& t, const LdsView& v, uint32_t a,
-                                         bool want_code) {
-    Lookup r;
-    if constexpr (KIND == KK_SCAN) {
-        r.code = scan_owner(t, v, a);
-        r.in = r.code != 0;
-    } else {
-        uint32_t j = interval_of<KIND>(t, v, a);
-        r.in = (v.member[j >> 5] >> (j & 31)) & 1u;
-        r.code = want_code ? t.owner[j] : 0u;
+// Membership of a in the union of the prefixes, from the in/out index (LDS).
+__device__ __forceinline__ uint32_t inout_of(const DevTable& t, const uint32_t* io, uint32_t a) {
+    const uint32_t k = a >> 16;
+    const uint32_t f = io[k >> 4];
+    const uint32_t sh = (k & 15u) * 2;
+    const uint32_t st = (f >> sh) & 3u;
+    if (st < 2u) return st;
+    const uint32_t cut = (f >> 1) & ~f & 0x55555555u;  // bit 2i: block i of the word is cut
+    const uint32_t r = u16_at(io + t.io_rank, k >> 4) + __popc(cut & ((1u << sh) - 1u));
+    uint32_t lo = u16_at(io + t.io_start, r);
+    uint32_t hi = u16_at(io + t.io_start, r + 1);
+    const uint32_t first = lo;
+    const uint32_t low = a & 0xFFFFu;
+    while (lo < hi) {  // number of boundaries <= low
+        const uint32_t mid = (lo + hi) >> 1;
+        if (u16_at(io + t.io_list, mid) <= low) lo = mid + 1;
+        else hi = mid;
     }
-    return r;
+    const uint32_t s0 = (io[t.io_sbit + (r >> 5)] >> (r & 31u)) & 1u;
+    return s0 ^ ((lo - first) & 1u);
+}
+
+template <uint32_t KIND, int N>
+__device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, const uint32_t* a,
+                                        bool want_code, uint32_t* in, uint32_t* code) {
+    if constexpr (KIND == KK_INOUT) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            in[q] = inout_of(t, v.io, a[q]);
+            code[q] = 0;
+        }
+    } else if constexpr (KIND == KK_SCAN) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            code[q] = scan_owner(t, v, a[q]);
+            in[q] = code[q] != 0;
+        }
+    } else {
+        uint32_t need = 0xFFFFFFFFu;
+        uint32_t st[N];
+        if (!want_code && t.filter_lds) {
+            need = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                st[q] = (v.filter[a[q] >> 20] >> (((a[q] >> 16) & 15u) * 2)) & 3u;
+                need |= (st[q] == 2u ? 1u : 0u) << q;
+            }
+        }
+        if (need) {
+            uint32_t j[N];
+            intervals<KIND, N>(t, v, a, j, need);
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                if (!((need >> q) & 1u)) continue;
+                in[q] = (v.member[j[q] >> 5] >> (j[q] & 31)) & 1u;
+                code[q] = want_code ? t.owner[j[q]] : 0u;
+            }
+        }
+        if (!want_code && t.filter_lds) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                if (st[q] < 2u) in[q] = st[q];
+                code[q] = 0;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// the pass kernel
+// binning
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t bin_of(uint32_t x, uint32_t width, uint64_t magic) {
     // floor(x / width) for 32-bit x: with c = ceil(2^64 / width) the high 64
@@ -157,94 +315,126 @@ __device__ __forceinline__ uint32_t bin_of(uint32_t x, uint32_t width, uint64_t 
     return (uint32_t)(u >> 32);
 }
 
+// In-window test and bin of one session (the Map step's key).
+__device__ __forceinline__ bool in_window(const PassParams& p, uint32_t ts, uint32_t& bin) {
+    bin = bin_of(ts - p.t0, p.width, p.magic);
+    return ts >= p.t0 && bin < p.n_bins;
+}
+
 struct Dropped {
     unsigned long long c[4];
     unsigned long long b[4];
-};
-
-template <bool HIST>
-__device__ __forceinline__ void account(const PassParams& p, uint32_t lab, uint32_t ts,
-                                        uint64_t nbytes, Dropped& d) {
-    if constexpr (HIST) {
-        uint32_t x = ts - p.t0;
-        uint32_t b = bin_of(x, p.width, p.magic);
-        if (ts >= p.t0 && b < p.n_bins) {
-            uint64_t k = (uint64_t)lab * p.n_bins + b;
-            __hip_atomic_fetch_add(p.count + k, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(p.hbytes + k, (unsigned long long)nbytes, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+    __device__ __forceinline__ void add(uint32_t lab, uint64_t nbytes) {
 #pragma unroll
-            for (uint32_t l = 0; l < 4; ++l) {  // constant indices: stays in registers
-                const bool h = lab == l;
-                d.c[l] += h ? 1ull : 0ull;
-                d.b[l] += h ? nbytes : 0ull;
+        for (uint32_t l = 0; l < 4; ++l) {  // constant indices: stays in registers
+            const bool h = lab == l;
+            c[l] += h ? 1ull : 0ull;
+            b[l] += h ? nbytes : 0ull;
+        }
+    }
+    __device__ __forceinline__ void flush(unsigned long long* out) const {
+        if (!out) return;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            if (c[l]) {
+                atomicAdd(out + 2 * l, c[l]);
+                atomicAdd(out + 2 * l + 1, b[l]);
             }
         }
     }
-}
+};
 
-template <uint32_t KIND, bool HIST>
-__device__ __forceinline__ void one_session(const PassParams& p, const LdsView& v, uint64_t i,
-                                            Dropped& d) {
-    uint32_t lab;
-    if (p.pos_out) {
-        if constexpr (KIND != KK_SCAN && KIND != KK_LABEL_IN)
-            p.pos_out[i] = interval_of<KIND>(p.t, v, p.src[i]);
+enum HistMode : int {
+    H_NONE = 0,     // labels / institutions / positions only
+    H_ATOMIC = 1,   // device-scope atomics into the output bins
+    H_PRIVATE = 2   // whole histogram privatised in LDS per workgroup
+};
+
+// LDS histogram of the private mode: counts u32 [4][n_bins], bytes u64 [4][n_bins].
+struct PrivHist {
+    uint32_t* c;
+    unsigned long long* b;
+};
+
+template <int HM>
+__device__ __forceinline__ void account(const PassParams& p, const PrivHist& h, uint32_t lab,
+                                        uint32_t ts, uint64_t nbytes, Dropped& d) {
+    if constexpr (HM == H_NONE) return;
+    uint32_t b;
+    if (!in_window(p, ts, b)) {
+        d.add(lab, nbytes);
         return;
     }
+    const uint64_t k = (uint64_t)lab * p.n_bins + b;
+    if constexpr (HM == H_ATOMIC) {
+        __hip_atomic_fetch_add(p.count + k, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(p.hbytes + k, (unsigned long long)nbytes, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        atomicAdd(h.c + k, 1u);
+        atomicAdd(h.b + k, (unsigned long long)nbytes);
+    }
+}
+
+// Label of session i (scalar path); stores label / institutions when asked.
+template <uint32_t KIND>
+__device__ __forceinline__ uint32_t label1(const PassParams& p, const LdsView& v, uint64_t i) {
+    const uint32_t a[2] = {p.src[i], p.dst[i]};
+    const bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
+    uint32_t in[2], code[2];
+    lookups<KIND, 2>(p.t, v, a, wc, in, code);
+    const uint32_t lab = in[0] | (in[1] << 1);
+    if (p.label_out) p.label_out[i] = (uint8_t)lab;
+    if (p.src_inst) p.src_inst[i] = code[0] ? p.t.inst[code[0] - 1] : SINET_NO_INST;
+    if (p.dst_inst) p.dst_inst[i] = code[1] ? p.t.inst[code[1] - 1] : SINET_NO_INST;
+    return lab;
+}
+
+template <uint32_t KIND, int HM>
+__device__ __forceinline__ void one_session(const PassParams& p, const LdsView& v,
+                                            const PrivHist& h, uint64_t i, Dropped& d) {
+    if (p.pos_out) {
+        if constexpr (KIND != KK_SCAN && KIND != KK_LABEL_IN && KIND != KK_INOUT) {
+            const uint32_t a = p.src[i];
+            uint32_t j;
+            intervals<KIND, 1>(p.t, v, &a, &j);
+            p.pos_out[i] = j;
+        }
+        return;
+    }
+    uint32_t lab;
     if constexpr (KIND == KK_LABEL_IN) {
         lab = p.label_in[i] & 3u;
     } else {
-        bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
-        Lookup ls = lookup<KIND>(p.t, v, p.src[i], wc);
-        Lookup ld = lookup<KIND>(p.t, v, p.dst[i], wc);
-        lab = ls.in | (ld.in << 1);
-        if (p.label_out) p.label_out[i] = (uint8_t)lab;
-        if (p.src_inst) p.src_inst[i] = ls.code ? p.t.inst[ls.code - 1] : SINET_NO_INST;
-        if (p.dst_inst) p.dst_inst[i] = ld.code ? p.t.inst[ld.code - 1] : SINET_NO_INST;
+        lab = label1<KIND>(p, v, i);
     }
-    if constexpr (HIST) account<HIST>(p, lab, p.ts[i], p.bytes[i], d);
+    if constexpr (HM != H_NONE) account<HM>(p, h, lab, p.ts[i], p.bytes[i], d);
 }
 
-template <uint32_t KIND, bool HIST>
-__device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView& v, uint64_t g,
-                                              Dropped& d) {
-    const uint64_t i = g * 4;
-    if (p.pos_out) {
-        if constexpr (KIND != KK_SCAN && KIND != KK_LABEL_IN) {
-            uint4 a = *reinterpret_cast<const uint4*>(p.src + i);
-            uint4 o;
-            o.x = interval_of<KIND>(p.t, v, a.x);
-            o.y = interval_of<KIND>(p.t, v, a.y);
-            o.z = interval_of<KIND>(p.t, v, a.z);
-            o.w = interval_of<KIND>(p.t, v, a.w);
-            *reinterpret_cast<uint4*>(p.pos_out + i) = o;
-        }
-        return;
-    }
-    uint32_t lab[4];
+// Labels of four consecutive sessions starting at i from their loaded source
+// and destination words (or the given labels); stores labels / institutions
+// when asked.
+template <uint32_t KIND>
+__device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView& v, uint64_t i,
+                                             uint4 s, uint4 t, uint32_t l4, uint32_t lab[4]) {
     if constexpr (KIND == KK_LABEL_IN) {
-        uint32_t l4 = *reinterpret_cast<const uint32_t*>(p.label_in + i);
 #pragma unroll
         for (int k = 0; k < 4; ++k) lab[k] = (l4 >> (8 * k)) & 3u;
     } else {
-        uint4 s = *reinterpret_cast<const uint4*>(p.src + i);
-        uint4 t = *reinterpret_cast<const uint4*>(p.dst + i);
-        uint32_t sa[4] = {s.x, s.y, s.z, s.w};
-        uint32_t da[4] = {t.x, t.y, t.z, t.w};
-        bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
+        // sources and destinations of the four sessions, looked up together
+        const uint32_t a[8] = {s.x, s.y, s.z, s.w, t.x, t.y, t.z, t.w};
+        const bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
+        uint32_t in[8], code[8];
+        lookups<KIND, 8>(p.t, v, a, wc, in, code);
         uint32_t sc[4], dc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            Lookup ls = lookup<KIND>(p.t, v, sa[k], wc);
-            Lookup ld = lookup<KIND>(p.t, v, da[k], wc);
-            lab[k] = ls.in | (ld.in << 1);
-            sc[k] = ls.code;
-            dc[k] = ld.code;
+            lab[k] = in[k] | (in[4 + k] << 1);
+            sc[k] = code[k];
+            dc[k] = code[4 + k];
         }
         if (p.label_out) {
-            uint32_t packed = lab[0] | (lab[1] << 8) | (lab[2] << 16) | (lab[3] << 24);
+            const uint32_t packed = lab[0] | (lab[1] << 8) | (lab[2] << 16) | (lab[3] << 24);
             *reinterpret_cast<uint32_t*>(p.label_out + i) = packed;
         }
         if (p.src_inst) {
@@ -264,20 +454,52 @@ __device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView
             *reinterpret_cast<uint4*>(p.dst_inst + i) = o;
         }
     }
-    if constexpr (HIST) {
-        uint4 ts = *reinterpret_cast<const uint4*>(p.ts + i);
-        ulonglong2 b01 = *reinterpret_cast<const ulonglong2*>(p.bytes + i);
-        ulonglong2 b23 = *reinterpret_cast<const ulonglong2*>(p.bytes + i + 2);
-        account<HIST>(p, lab[0], ts.x, b01.x, d);
-        account<HIST>(p, lab[1], ts.y, b01.y, d);
-        account<HIST>(p, lab[2], ts.z, b23.x, d);
-        account<HIST>(p, lab[3], ts.w, b23.y, d);
+}
+
+template <uint32_t KIND>
+__device__ __forceinline__ void labels4(const PassParams& p, const LdsView& v, uint64_t i,
+                                        uint32_t lab[4]) {
+    uint4 s = make_uint4(0, 0, 0, 0), t = s;
+    uint32_t l4 = 0;
+    if constexpr (KIND == KK_LABEL_IN) {
+        l4 = *reinterpret_cast<const uint32_t*>(p.label_in + i);
+    } else {
+        s = *reinterpret_cast<const uint4*>(p.src + i);
+        t = *reinterpret_cast<const uint4*>(p.dst + i);
+    }
+    labels4_from<KIND>(p, v, i, s, t, l4, lab);
+}
+
+template <uint32_t KIND, int HM>
+__device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView& v,
+                                              const PrivHist& h, uint64_t i, Dropped& d) {
+    if (p.pos_out) {
+        if constexpr (KIND != KK_SCAN && KIND != KK_LABEL_IN && KIND != KK_INOUT) {
+            const uint4 a4 = *reinterpret_cast<const uint4*>(p.src + i);
+            const uint32_t a[4] = {a4.x, a4.y, a4.z, a4.w};
+            uint32_t j[4];
+            intervals<KIND, 4>(p.t, v, a, j);
+            *reinterpret_cast<uint4*>(p.pos_out + i) = make_uint4(j[0], j[1], j[2], j[3]);
+        }
+        return;
+    }
+    uint32_t lab[4];
+    labels4<KIND>(p, v, i, lab);
+    if constexpr (HM != H_NONE) {
+        const uint4 ts = *reinterpret_cast<const uint4*>(p.ts + i);
+        const ulonglong2 b01 = *reinterpret_cast<const ulonglong2*>(p.bytes + i);
+        const ulonglong2 b23 = *reinterpret_cast<const ulonglong2*>(p.bytes + i + 2);
+        account<HM>(p, h, lab[0], ts.x, b01.x, d);
+        account<HM>(p, h, lab[1], ts.y, b01.y, d);
+        account<HM>(p, h, lab[2], ts.z, b23.x, d);
+        account<HM>(p, h, lab[3], ts.w, b23.y, d);
     }
 }
 
 // Stage the table's hot arrays into LDS (layout chosen on the host).
+// Returns the view; *words receives the number of 32-bit words used.
 template <uint32_t KIND>
-__device__ LdsView stage_lds(const DevTable& t, uint32_t* lds) {
+__device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) {
     LdsView v{};
     uint32_t off = 0;
     auto copy = [&](const uint32_t* src, uint32_t n) -> const uint32_t* {
@@ -286,11 +508,14 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds) {
         off += n;
         return dst;
     };
-    if constexpr (KIND == KK_SCAN) {
+    if constexpr (KIND == KK_INOUT) {
+        v.io = copy(t.io, t.io_words);
+    } else if constexpr (KIND == KK_SCAN) {
         v.cb = copy(t.cb, t.n_prefix);
         v.mask = copy(t.mask, t.n_prefix);
         v.len = copy(t.len, t.n_prefix);
     } else if constexpr (KIND != KK_LABEL_IN) {
+        v.filter = t.filter_lds ? copy(t.filter, kFilterWords) : t.filter;
         if constexpr (KIND == KK_BSEARCH) v.top = copy(t.top, t.n_top);
         if constexpr (KIND == KK_PLA) {
             v.knot = copy(t.knot, t.segments);
@@ -298,60 +523,471 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds) {
                 copy(reinterpret_cast<const uint32_t*>(t.pla_c), t.segments));
             v.g = reinterpret_cast<const float*>(
                 copy(reinterpret_cast<const uint32_t*>(t.pla_g), t.segments));
+            v.radix = copy(t.radix, radix_words(t.radix_bits));
         }
         if constexpr (KIND == KK_MLP)
             v.w = reinterpret_cast<const float*>(
                 copy(reinterpret_cast<const uint32_t*>(t.mlp), SINET_MLP_PARAMS));
         v.member = t.lds_member_words ? copy(t.member, t.lds_member_words) : t.member;
     }
+    *words = off;
     __syncthreads();
     return v;
 }
 
-template <uint32_t KIND, bool HIST, bool VEC>
-__global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p) {
+// ---------------------------------------------------------------------------
+// k_pass: one pass over the sessions.
+//   H_NONE    labels / institutions / positions;
+//   H_PRIVATE the whole (small) histogram lives in LDS per workgroup and is
+//             merged into the output bins with atomics at the end;
+//   H_ATOMIC  with far.list: only the sessions the partitioned path flagged
+//             as far (see k_stage1), merged with device-scope atomics after
+//             the block reduction wrote the bins; without: every session.
+// ---------------------------------------------------------------------------
+template <uint32_t KIND, int HM, bool VEC>
+__global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
     extern __shared__ uint32_t lds[];
-    const LdsView v = stage_lds<KIND>(p.t, lds);
-
-    // XCD-contiguous split of the tiles (one tile = 4 sessions per lane).
-    const uint64_t groups = (p.n + 3) / 4;
-    const uint64_t tile = blockDim.x;
-    const uint64_t n_tiles = (groups + tile - 1) / tile;
-    const uint32_t W = gridDim.x;
-    const uint32_t xcd = blockIdx.x % kXcds;
-    const uint32_t lid = blockIdx.x / kXcds;
-    const uint32_t per = W / kXcds, rem = W % kXcds;
-    const uint32_t nx = per + (xcd < rem ? 1u : 0u);
-    const uint64_t cum = (uint64_t)xcd * per + min(xcd, rem);
-    const uint64_t T0 = n_tiles * cum / W;
-    const uint64_t T1 = n_tiles * (cum + nx) / W;
-
+    uint32_t used = 0;
+    const LdsView v = stage_lds<KIND>(p.t, lds, &used);
+    PrivHist h{nullptr, nullptr};
+    if constexpr (HM == H_PRIVATE) {
+        used = (used + 1) & ~1u;
+        h.b = reinterpret_cast<unsigned long long*>(lds + used);
+        h.c = lds + used + 2 * 4 * p.n_bins;
+        for (uint32_t k = threadIdx.x; k < 4 * p.n_bins; k += blockDim.x) {
+            h.b[k] = 0;
+            h.c[k] = 0;
+        }
+        __syncthreads();
+    }
     Dropped d{};
-    for (uint64_t tl = T0 + lid; tl < T1; tl += nx) {
-        const uint64_t g = tl * tile + threadIdx.x;
-        if (g >= groups) continue;
-        if (VEC && g * 4 + 4 <= p.n) {
-            four_sessions<KIND, HIST>(p, v, g, d);
-        } else {
-            for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i) one_session<KIND, HIST>(p, v, i, d);
+    if (HM == H_ATOMIC && far.list) {
+        const uint32_t nfar = *far.count;
+        for (uint32_t q = blockIdx.x; q < nfar; q += gridDim.x) {
+            const uint64_t c = far.list[q];
+            for (uint32_t s = threadIdx.x; s < kChunk; s += blockDim.x) {
+                const uint64_t i = c * kChunk + s;
+                if (i < p.n && ((far.bits[c * (kChunk / 32) + s / 32] >> (s & 31)) & 1u))
+                    one_session<KIND, HM>(p, v, h, i, d);
+            }
+        }
+    } else {
+        // XCD-contiguous split of the tiles (one tile = 4 sessions per lane).
+        const uint64_t groups = (p.n + 3) / 4;
+        const uint64_t tile = blockDim.x;
+        const uint64_t n_tiles = (groups + tile - 1) / tile;
+        const uint32_t W = gridDim.x;
+        const uint32_t xcd = blockIdx.x % kXcds;
+        const uint32_t lid = blockIdx.x / kXcds;
+        const uint32_t per = W / kXcds, rem = W % kXcds;
+        const uint32_t nx = per + (xcd < rem ? 1u : 0u);
+        const uint64_t cum = (uint64_t)xcd * per + min(xcd, rem);
+        const uint64_t T0 = n_tiles * cum / W;
+        const uint64_t T1 = n_tiles * (cum + nx) / W;
+        for (uint64_t tl = T0 + lid; tl < T1; tl += nx) {
+            const uint64_t g = tl * tile + threadIdx.x;
+            if (g >= groups) continue;
+            if (VEC && g * 4 + 4 <= p.n) {
+                four_sessions<KIND, HM>(p, v, h, g * 4, d);
+            } else {
+                for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
+                    one_session<KIND, HM>(p, v, h, i, d);
+            }
         }
     }
-    if constexpr (HIST) {
-        if (p.dropped) {
+    if constexpr (HM != H_NONE) d.flush(p.dropped);
+    if constexpr (HM == H_PRIVATE) {
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < 4 * p.n_bins; k += blockDim.x) {
+            if (h.c[k]) {
+                __hip_atomic_fetch_add(p.count + k, (unsigned long long)h.c[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(p.hbytes + k, h.b[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned histogram: the two-stage map-reduce, both stages on the GPU.
+//
+// Stage 1 (k_stage1, fused with discrimination): a workgroup takes a chunk of
+// kChunk consecutive sessions, labels them and maps each in-window session to
+// (block = bin / kBlockBins, offset, label).  Sessions are counting-sorted in
+// LDS by block relative to the chunk's first block (a window of kWin blocks)
+// and written as 4-byte records, grouped by block, into the chunk's own slot
+// range; the chunk's directory lists (block, first slot, count) for every
+// block it touched.  Near time-sorted input (the paper's session logs)
+// touches few blocks per chunk.
+// Segment index: per-block directory counts, an exclusive scan, and a fill
+// that groups the directory entries by block (k_fill).
+// Stage 2 (k_stage2): one workgroup per block accumulates its segments'
+// records in LDS and writes the block's count and byte bins once, with
+// coalesced stores; no zero-fill and no global atomics.
+// Far path: a session outside its chunk's block window, with bytes >= 2^52,
+// or beyond the chunk's big-value slots is flagged and merged afterwards by
+// k_pass<H_ATOMIC> with global atomics, so any input stays exact.
+//
+// Record: label (2 bits) | offset in block (10) | big flag (1) | payload (19):
+// the byte count itself when < 2^19, else an index into the chunk's
+// 64-bit big-value slots.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+    for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o));
+    return x;
+}
+
+// Raw column words of one lane's four sessions (loaded one chunk ahead).
+struct Raw4 {
+    uint4 src, dst, ts;
+    ulonglong2 b01, b23;
+    uint32_t l4;
+};
+
+template <uint32_t KIND>
+__device__ __forceinline__ void load4(const PassParams& p, uint64_t i, Raw4& r) {
+    if constexpr (KIND == KK_LABEL_IN) {
+        r.l4 = *reinterpret_cast<const uint32_t*>(p.label_in + i);
+    } else {
+        r.src = *reinterpret_cast<const uint4*>(p.src + i);
+        r.dst = *reinterpret_cast<const uint4*>(p.dst + i);
+    }
+    r.ts = *reinterpret_cast<const uint4*>(p.ts + i);
+    r.b01 = *reinterpret_cast<const ulonglong2*>(p.bytes + i);
+    r.b23 = *reinterpret_cast<const ulonglong2*>(p.bytes + i + 2);
+}
+
+template <uint32_t KIND>
+__global__ void __launch_bounds__(kStage1Block) k_stage1(PassParams p, PartWs w) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_cnt[kWin];
+    __shared__ uint32_t s_base[kWin];
+    __shared__ uint32_t s_far[kChunk / 32];
+    __shared__ uint32_t s_wmin[kStage1Block / 64];
+    __shared__ uint32_t s_nbig, s_nfar, s_bmin;
+    uint32_t used = 0;
+    const LdsView v = stage_lds<KIND>(p.t, lds, &used);
+    Dropped d{};
+    const uint32_t tid = threadIdx.x;
+    const uint64_t n_chunks = w.n_chunks;
+    // a chunk is "full" when its 4096 sessions exist and vector loads are allowed
+    auto full = [&](uint64_t c) { return w.vec && (c + 1) * kChunk <= p.n; };
+    Raw4 cur{}, nxt{};
+    uint64_t c = blockIdx.x;
+    if (c < n_chunks && full(c)) load4<KIND>(p, c * kChunk + (uint64_t)tid * 4, cur);
+    for (; c < n_chunks; c += gridDim.x) {
+        const uint64_t cn = c + gridDim.x;
+        if (cn < n_chunks && full(cn)) load4<KIND>(p, cn * kChunk + (uint64_t)tid * 4, nxt);
+        const uint64_t i0 = c * kChunk + (uint64_t)tid * 4;
+        uint32_t lab[4], ts[4], bin[4];
+        unsigned long long by[4];
+        bool inw[4];
+        if (full(c)) {
+            labels4_from<KIND>(p, v, i0, cur.src, cur.dst, cur.l4, lab);
+            ts[0] = cur.ts.x; ts[1] = cur.ts.y; ts[2] = cur.ts.z; ts[3] = cur.ts.w;
+            by[0] = cur.b01.x; by[1] = cur.b01.y; by[2] = cur.b23.x; by[3] = cur.b23.y;
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                if (d.c[l]) {
-                    atomicAdd(p.dropped + 2 * l, d.c[l]);
-                    atomicAdd(p.dropped + 2 * l + 1, d.b[l]);
+            for (int k = 0; k < 4; ++k) inw[k] = in_window(p, ts[k], bin[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t i = i0 + k;
+                inw[k] = false;
+                lab[k] = 0;
+                ts[k] = 0;
+                by[k] = 0;
+                bin[k] = 0;
+                if (i < p.n) {
+                    if constexpr (KIND == KK_LABEL_IN) {
+                        lab[k] = p.label_in[i] & 3u;
+                    } else {
+                        lab[k] = label1<KIND>(p, v, i);
+                    }
+                    ts[k] = p.ts[i];
+                    by[k] = p.bytes[i];
+                    inw[k] = in_window(p, ts[k], bin[k]);
                 }
             }
+        }
+        cur = nxt;
+        uint32_t blk[4];
+        uint32_t mymin = 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            blk[k] = bin[k] / kBlockBins;
+            if (inw[k]) mymin = min(mymin, blk[k]);
+            else if (i0 + k < p.n) d.add(lab[k], by[k]);
+        }
+        mymin = wave_min(mymin);
+        if ((tid & 63) == 0) s_wmin[tid >> 6] = mymin;
+        if (tid < kWin) s_cnt[tid] = 0;
+        for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block) s_far[k] = 0;
+        if (tid == 0) {
+            s_nbig = 0;
+            s_nfar = 0;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t m = tid < kStage1Block / 64 ? s_wmin[tid] : 0xFFFFFFFFu;
+            m = wave_min(m);
+            if (tid == 0) s_bmin = m;
+        }
+        __syncthreads();
+        const uint32_t bmin = s_bmin;
+        uint32_t rank[4], bigi[4];
+        bool loc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t r = blk[k] - bmin;
+            loc[k] = inw[k] && r < kWin && by[k] < (1ull << 52);
+            bigi[k] = 0xFFFFFFFFu;
+            if (loc[k] && by[k] >= kSmallMax) {
+                bigi[k] = atomicAdd(&s_nbig, 1u);
+                if (bigi[k] >= kBigSlots) loc[k] = false;
+            }
+            rank[k] = loc[k] ? atomicAdd(&s_cnt[r], 1u) : 0u;
+            if (inw[k] && !loc[k]) {
+                const uint32_t sidx = tid * 4 + k;
+                atomicOr(&s_far[sidx >> 5], 1u << (sidx & 31));
+                atomicAdd(&s_nfar, 1u);
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {  // exclusive scan of the kWin (= 64) block counts, one wave
+            const uint32_t x = s_cnt[tid];
+            uint32_t inc = x;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
+                if ((int)tid >= o) inc += y;
+            }
+            s_base[tid] = inc - x;
+            // directory entry of every touched block
+            const bool nz = x != 0;
+            const unsigned long long m = __ballot(nz);
+            const uint32_t e = __popcll(m & ((1ull << tid) - 1ull));
+            if (nz) {
+                const uint32_t b = bmin + tid;
+                w.dir[c * kWin + e] = make_uint4(b, (uint32_t)(c * kChunk) + (inc - x), x, 0u);
+                atomicAdd(w.seg_count + b, 1u);
+            }
+            if (tid == 0) w.nd[c] = (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        const uint64_t slot0 = c * kChunk;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!loc[k]) continue;
+            const uint32_t r = blk[k] - bmin;
+            const uint32_t off = bin[k] - blk[k] * kBlockBins;
+            uint32_t rec = (lab[k] << 30) | (off << 20);
+            if (bigi[k] != 0xFFFFFFFFu) {
+                rec |= (1u << 19) | bigi[k];
+                w.big[c * kBigSlots + bigi[k]] = by[k];
+            } else {
+                rec |= (uint32_t)by[k];
+            }
+            w.rec[slot0 + s_base[r] + rank[k]] = rec;
+        }
+        if (s_nfar) {
+            for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block)
+                w.farbits[c * (kChunk / 32) + k] = s_far[k];
+            if (tid == 0) w.farlist[atomicAdd(w.farcount, 1u)] = (uint32_t)c;
+        }
+        __syncthreads();
+    }
+    d.flush(p.dropped);
+}
+
+// Exclusive scan of n u32 counts into out[0..n] (out[n] = total), in three
+// launches: per-tile sums, a single-workgroup scan of the tile sums, and the
+// per-tile rescan.  kScanTile elements per workgroup of 1024 threads.
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* s_w) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
+        if ((int)lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        const uint32_t nw = blockDim.x >> 6;
+        uint32_t v = lane < nw ? s_w[lane] : 0u;
+        uint32_t vi = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)vi, o);
+            if ((int)lane >= o) vi += y;
+        }
+        if (lane < nw) s_w[lane] = vi - v;
+    }
+    __syncthreads();
+    const uint32_t r = inc + s_w[wid];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n,
+                                                     uint32_t* __restrict__ tile_sum) {
+    __shared__ uint32_t s_w[16];
+    const uint64_t i = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t x = i < n ? in[i] : 0u;
+    const uint32_t inc = block_incl_scan(x, s_w);
+    if (threadIdx.x == 1023) tile_sum[blockIdx.x] = inc;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* __restrict__ tile_sum, uint32_t nt) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < nt; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t x = i < nt ? tile_sum[i] : 0u;
+        const uint32_t inc = block_incl_scan(x, s_w);
+        const uint32_t carry = s_carry;
+        if (i < nt) tile_sum[i] = carry + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = carry + inc;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_final(const uint32_t* __restrict__ in, uint32_t n,
+                                                     const uint32_t* __restrict__ tile_off,
+                                                     uint32_t* __restrict__ out) {
+    __shared__ uint32_t s_w[16];
+    const uint64_t i = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t x = i < n ? in[i] : 0u;
+    const uint32_t inc = block_incl_scan(x, s_w);
+    const uint32_t exc = tile_off[blockIdx.x] + inc - x;
+    if (i < n) out[i] = exc;
+    if (i == n) out[n] = exc;  // the total (x = 0 there)
+}
+
+// Group the directory entries by block: segs[seg_off[b] ..] = (first slot,
+// count).  Consumes seg_count back to zero.
+__global__ void k_fill(PartWs w) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < w.n_chunks * kWin;
+         q += stride) {
+        const uint64_t c = q / kWin;
+        const uint32_t e = (uint32_t)(q % kWin);
+        if (e >= w.nd[c]) continue;
+        const uint4 d = w.dir[q];
+        const uint32_t pos = w.seg_off[d.x] + atomicSub(w.seg_count + d.x, 1u) - 1u;
+        w.segs[pos] = make_uint2(d.y, d.z);
+    }
+}
+
+// One workgroup per block of kBlockBins bins (all four labels).  The block's
+// segments are taken kSegBatch at a time: their (first slot, count) pairs and
+// a prefix sum of the counts go to LDS, and every lane then walks the batch's
+// records by flat index, so all record loads of a batch are in flight at once.
+__global__ void __launch_bounds__(kStage2Block) k_stage2(PartWs w, unsigned long long* count,
+                                                        unsigned long long* hbytes, uint32_t n_bins,
+                                                        int accumulate) {
+    __shared__ unsigned long long s_b[4 * kBlockBins];
+    __shared__ uint32_t s_c[4 * kBlockBins];
+    __shared__ uint32_t s_start[kSegBatch];
+    __shared__ uint32_t s_pref[kSegBatch + 1];
+    __shared__ uint32_t s_w[kStage2Block / 64];
+    const uint32_t blk = blockIdx.x;
+    for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
+        s_b[k] = 0;
+        s_c[k] = 0;
+    }
+    const uint32_t s0 = w.seg_off[blk], s1 = w.seg_off[blk + 1];
+    for (uint32_t sb = s0; sb < s1; sb += kSegBatch) {
+        const uint32_t nseg = min((uint32_t)kSegBatch, s1 - sb);
+        uint32_t cnt = 0;
+        if (threadIdx.x < nseg) {
+            const uint2 sg = w.segs[sb + threadIdx.x];
+            s_start[threadIdx.x] = sg.x;
+            cnt = sg.y;
+        }
+        const uint32_t inc = block_incl_scan(cnt, s_w);  // includes the barriers
+        if (threadIdx.x < nseg) s_pref[threadIdx.x] = inc - cnt;
+        if (threadIdx.x == kStage2Block - 1) s_pref[nseg] = inc;
+        __syncthreads();
+        const uint32_t total = s_pref[nseg];
+        // kRecUnroll independent record loads in flight per lane
+        for (uint32_t r0 = 0; r0 < total; r0 += kStage2Block * kRecUnroll) {
+            uint32_t rec[kRecUnroll], slot[kRecUnroll];
+#pragma unroll
+            for (int u = 0; u < kRecUnroll; ++u) {
+                const uint32_t r = r0 + u * kStage2Block + threadIdx.x;
+                slot[u] = 0xFFFFFFFFu;
+                rec[u] = 0;
+                if (r < total) {
+                    // segment j holding flat record r: last j with s_pref[j] <= r
+                    uint32_t lo = 0, n = nseg;
+                    while (n > 1) {
+                        const uint32_t half = n >> 1;
+                        lo = s_pref[lo + half] <= r ? lo + half : lo;
+                        n -= half;
+                    }
+                    slot[u] = s_start[lo] + (r - s_pref[lo]);
+                    rec[u] = w.rec[slot[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRecUnroll; ++u) {
+                if (slot[u] == 0xFFFFFFFFu) continue;
+                const uint32_t key = rec[u] >> 20;  // label * kBlockBins + offset
+                const unsigned long long v =
+                    (rec[u] >> 19) & 1u
+                        ? w.big[(uint64_t)(slot[u] / kChunk) * kBigSlots + (rec[u] & 0x7FFFFu)]
+                        : (unsigned long long)(rec[u] & 0x7FFFFu);
+                atomicAdd(&s_c[key], 1u);
+                atomicAdd(&s_b[key], v);
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // write the block: two consecutive bins per lane (16-byte stores when the
+    // label row is 16-byte aligned, which holds when n_bins is even)
+    const uint64_t b0 = (uint64_t)blk * kBlockBins;
+    const bool pairs = (n_bins & 1u) == 0 && (((uintptr_t)count | (uintptr_t)hbytes) & 15u) == 0;
+    if (pairs) {
+        for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
+            const uint32_t e = 2 * k;
+            const uint32_t lab = e / kBlockBins, off = e % kBlockBins;
+            const uint64_t bin = b0 + off;
+            if (bin >= n_bins) continue;  // n_bins even: bin + 1 is inside too
+            const uint64_t o = (uint64_t)lab * n_bins + bin;
+            ulonglong2 c = make_ulonglong2(s_c[e], s_c[e + 1]);
+            ulonglong2 b = make_ulonglong2(s_b[e], s_b[e + 1]);
+            if (accumulate) {
+                const ulonglong2 oc = *reinterpret_cast<const ulonglong2*>(count + o);
+                const ulonglong2 ob = *reinterpret_cast<const ulonglong2*>(hbytes + o);
+                c.x += oc.x; c.y += oc.y;
+                b.x += ob.x; b.y += ob.y;
+            }
+            *reinterpret_cast<ulonglong2*>(count + o) = c;
+            *reinterpret_cast<ulonglong2*>(hbytes + o) = b;
+        }
+    } else {
+        for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
+            const uint32_t lab = k / kBlockBins, off = k % kBlockBins;
+            const uint64_t bin = b0 + off;
+            if (bin >= n_bins) continue;
+            const uint64_t o = (uint64_t)lab * n_bins + bin;
+            unsigned long long c = s_c[k], b = s_b[k];
+            if (accumulate) {
+                c += count[o];
+                b += hbytes[o];
+            }
+            count[o] = c;
+            hbytes[o] = b;
         }
     }
 }
 
 __global__ void k_zero(unsigned long long* __restrict__ p, uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t head = ((uintptr_t)p & 15) ? 1 : 0;  // p is 8-byte aligned
     if (head && i == 0) p[0] = 0;
     ulonglong2* q = reinterpret_cast<ulonglong2*>(p + head);
@@ -360,25 +996,48 @@ __global__ void k_zero(unsigned long long* __restrict__ p, uint64_t n) {
     if (i == 0 && ((n - head) & 1)) p[n - 1] = 0;
 }
 
+__global__ void k_zero32(uint32_t* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-using KernelFn = void (*)(PassParams);
+using PassFn = void (*)(PassParams, FarList);
+using Stage1Fn = void (*)(PassParams, PartWs);
 
 template <uint32_t KIND>
-static KernelFn pick_fn(bool hist, bool vec) {
-    if (hist) return vec ? k_pass<KIND, true, true> : k_pass<KIND, true, false>;
-    return vec ? k_pass<KIND, false, true> : k_pass<KIND, false, false>;
+static PassFn pass_fn(int hm, bool vec) {
+    switch (hm) {
+        case H_NONE: return vec ? k_pass<KIND, H_NONE, true> : k_pass<KIND, H_NONE, false>;
+        case H_ATOMIC: return vec ? k_pass<KIND, H_ATOMIC, true> : k_pass<KIND, H_ATOMIC, false>;
+        default: return vec ? k_pass<KIND, H_PRIVATE, true> : k_pass<KIND, H_PRIVATE, false>;
+    }
 }
 
-static KernelFn pick(uint32_t kind, bool hist, bool vec) {
+static PassFn pick_pass(uint32_t kind, int hm, bool vec) {
     switch (kind) {
-        case KK_SCAN: return pick_fn<KK_SCAN>(hist, vec);
-        case KK_BSEARCH: return pick_fn<KK_BSEARCH>(hist, vec);
-        case KK_TRIE: return pick_fn<KK_TRIE>(hist, vec);
-        case KK_PLA: return pick_fn<KK_PLA>(hist, vec);
-        case KK_MLP: return pick_fn<KK_MLP>(hist, vec);
-        case KK_LABEL_IN: return pick_fn<KK_LABEL_IN>(hist, vec);
+        case KK_SCAN: return pass_fn<KK_SCAN>(hm, vec);
+        case KK_BSEARCH: return pass_fn<KK_BSEARCH>(hm, vec);
+        case KK_TRIE: return pass_fn<KK_TRIE>(hm, vec);
+        case KK_PLA: return pass_fn<KK_PLA>(hm, vec);
+        case KK_MLP: return pass_fn<KK_MLP>(hm, vec);
+        case KK_INOUT: return pass_fn<KK_INOUT>(hm, vec);
+        case KK_LABEL_IN: return pass_fn<KK_LABEL_IN>(hm, vec);
+        default: return nullptr;
+    }
+}
+
+static Stage1Fn pick_stage1(uint32_t kind) {
+    switch (kind) {
+        case KK_SCAN: return k_stage1<KK_SCAN>;
+        case KK_BSEARCH: return k_stage1<KK_BSEARCH>;
+        case KK_TRIE: return k_stage1<KK_TRIE>;
+        case KK_PLA: return k_stage1<KK_PLA>;
+        case KK_MLP: return k_stage1<KK_MLP>;
+        case KK_INOUT: return k_stage1<KK_INOUT>;
+        case KK_LABEL_IN: return k_stage1<KK_LABEL_IN>;
         default: return nullptr;
     }
 }
@@ -399,15 +1058,17 @@ uint32_t device_cu_count() {
     return cus;
 }
 
-static int blocks_per_cu(KernelFn fn, int block, size_t lds) {
+static int blocks_per_cu(const void* fn, int block, size_t lds) {
     static std::mutex mu;
-    static std::map<std::tuple<void*, int, size_t, int>, int> cache;
+    static std::map<std::tuple<const void*, int, size_t, int>, int> cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    auto key = std::make_tuple((void*)fn, block, lds, dev);
+    auto key = std::make_tuple(fn, block, lds, dev);
     std::lock_guard<std::mutex> g(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess || nb < 1)
         nb = 1;
@@ -422,35 +1083,42 @@ uint64_t div_magic(uint32_t width) {
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 static bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
+// Can the 4-session vector loads/stores be used for these pointers?
+static bool vector_ok(const PassParams& p, uint32_t kind, bool hist) {
+    if (p.pos_out) return aligned16(p.src) && aligned16(p.pos_out);
+    bool vec = true;
+    if (kind == KK_LABEL_IN) vec = aligned4(p.label_in);
+    else vec = aligned16(p.src) && aligned16(p.dst);
+    if (p.label_out) vec = vec && aligned4(p.label_out);
+    if (p.src_inst) vec = vec && aligned16(p.src_inst);
+    if (p.dst_inst) vec = vec && aligned16(p.dst_inst);
+    if (hist) vec = vec && aligned16(p.ts) && aligned16(p.bytes);
+    return vec;
+}
+
+static sinet_status launch_k_pass(const PassParams& p, uint32_t kind, int hm, bool vec,
+                                  const FarList& far, size_t extra_lds, hipStream_t s) {
+    PassFn fn = pick_pass(kind, hm, vec);
+    if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no kernel for this lookup kind");
+    const size_t lds = (kind == KK_LABEL_IN ? 0 : p.t.lds_bytes) + extra_lds + 8;
+    if (lds > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
+    const int block = lds > 40 * 1024 ? 1024 : 256;
+    uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)fn, block, lds);
+    if (!far.list) {
+        const uint64_t tiles = ((p.n + 3) / 4 + block - 1) / block;
+        if (grid > tiles) grid = tiles;
+    }
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), lds, s, p, far);
+    return check_hip(hipGetLastError(), "pass kernel launch");
+}
+
 sinet_status launch_pass(const PassParams& p, uint32_t mode, hipStream_t s) {
     if (p.n == 0) return SINET_OK;
+    const uint32_t kind = (mode & PASS_LABEL_IN) ? (uint32_t)KK_LABEL_IN : p.t.kind;
     const bool hist = (mode & PASS_HIST) != 0;
-    uint32_t kind = (mode & PASS_LABEL_IN) ? (uint32_t)KK_LABEL_IN : p.t.kind;
-    bool vec = true;
-    if (p.pos_out) {
-        vec = aligned16(p.src) && aligned16(p.pos_out);
-    } else {
-        if (kind == KK_LABEL_IN) vec = vec && aligned4(p.label_in);
-        else vec = vec && aligned16(p.src) && aligned16(p.dst);
-        if (p.label_out) vec = vec && aligned4(p.label_out);
-        if (p.src_inst) vec = vec && aligned16(p.src_inst);
-        if (p.dst_inst) vec = vec && aligned16(p.dst_inst);
-        if (hist) vec = vec && aligned16(p.ts) && aligned16(p.bytes);
-    }
-    KernelFn fn = pick(kind, hist, vec);
-    if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no kernel for this lookup kind");
-    const size_t lds = kind == KK_LABEL_IN ? 0 : p.t.lds_bytes;
-    const int block = lds > 40 * 1024 ? 1024 : 256;
-    if (lds > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
-    const uint64_t tiles = ((p.n + 3) / 4 + block - 1) / block;
-    uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu(fn, block, lds);
-    if (grid > tiles) grid = tiles;
-    if (grid < 1) grid = 1;
-    if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)fn,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)lds);
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), lds, s, p);
-    return check_hip(hipGetLastError(), "pass kernel launch");
+    FarList none{};
+    return launch_k_pass(p, kind, hist ? H_ATOMIC : H_NONE, vector_ok(p, kind, hist), none, 0, s);
 }
 
 sinet_status launch_zero(unsigned long long* p, uint64_t n_words, hipStream_t s) {
@@ -461,6 +1129,182 @@ sinet_status launch_zero(unsigned long long* p, uint64_t n_words, hipStream_t s)
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n_words);
     return check_hip(hipGetLastError(), "zero kernel launch");
+}
+
+static sinet_status launch_zero32(uint32_t* p, uint64_t n, hipStream_t s) {
+    if (n == 0) return SINET_OK;
+    uint64_t blocks = (n + 255) / 256;
+    const uint64_t cap = (uint64_t)device_cu_count() * 8;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(k_zero32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return check_hip(hipGetLastError(), "zero kernel launch");
+}
+
+// ---- workspace of the partitioned histogram --------------------------------
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t part_ws_bytes(uint64_t n, uint32_t n_bins) {
+    const uint64_t nc = (n + kChunk - 1) / kChunk;
+    const uint64_t nb = (n_bins + kBlockBins - 1) / kBlockBins;
+    const uint64_t nt = (nb + 1 + 1023) / 1024;
+    return al256(4 * nc * kChunk) + al256(8 * nc * kBigSlots) + al256(16 * nc * kWin) +
+           al256(4 * nc) + al256(4 * nc * (kChunk / 32)) + al256(4 * (nc + 1)) + al256(4 * nb) +
+           al256(4 * (nb + 1)) + al256(8 * nc * kWin) + al256(4 * nt) + 256;
+}
+
+PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins) {
+    PartWs w{};
+    const uint64_t nc = (n + kChunk - 1) / kChunk;
+    const uint64_t nb = (n_bins + kBlockBins - 1) / kBlockBins;
+    const uint64_t nt = (nb + 1 + 1023) / 1024;
+    char* a = (char*)base;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char* r = a + o; o += al256(bytes); return (void*)r; };
+    w.rec = (uint32_t*)take(4 * nc * kChunk);
+    w.big = (unsigned long long*)take(8 * nc * kBigSlots);
+    w.dir = (uint4*)take(16 * nc * kWin);
+    w.nd = (uint32_t*)take(4 * nc);
+    w.farbits = (uint32_t*)take(4 * nc * (kChunk / 32));
+    w.farlist = (uint32_t*)take(4 * (nc + 1));
+    w.seg_count = (uint32_t*)take(4 * nb);
+    w.seg_off = (uint32_t*)take(4 * (nb + 1));
+    w.segs = (uint2*)take(8 * nc * kWin);
+    w.scan_tiles = (uint32_t*)take(4 * nt);
+    w.farcount = (uint32_t*)take(256);
+    w.n_chunks = nc;
+    w.n_blocks = (uint32_t)nb;
+    return w;
+}
+
+// Histogram of one stream by the partitioned path (workspace given).
+sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& w, int accumulate,
+                             hipStream_t s) {
+    PassParams p = p0;
+    const bool vec = vector_ok(p, kind, true);
+    PartWs wv = w;
+    wv.vec = vec ? 1u : 0u;
+    sinet_status st = launch_zero32(w.seg_count, w.n_blocks, s);
+    if (st == SINET_OK) st = launch_zero32(w.farcount, 1, s);
+    if (st != SINET_OK) return st;
+    Stage1Fn f1 = pick_stage1(kind);
+    const size_t lds = (kind == KK_LABEL_IN ? 0 : p.t.lds_bytes) + 8;
+    if (lds + 4096 > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
+    uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)f1, kStage1Block, lds);
+    if (grid > w.n_chunks) grid = w.n_chunks;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(f1, dim3((unsigned)grid), dim3(kStage1Block), lds, s, p, wv);
+    st = check_hip(hipGetLastError(), "stage-1 launch");
+    if (st != SINET_OK) return st;
+    const uint32_t nb = w.n_blocks;
+    const uint32_t ntiles = (nb + 1 + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(1024), 0, s, w.seg_count, nb, w.scan_tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, w.scan_tiles, ntiles);
+    hipLaunchKernelGGL(k_scan_final, dim3(ntiles), dim3(1024), 0, s, w.seg_count, nb, w.scan_tiles,
+                       w.seg_off);
+    uint64_t fb = (w.n_chunks * kWin + 255) / 256;
+    const uint64_t cap = (uint64_t)device_cu_count() * 16;
+    if (fb > cap) fb = cap;
+    if (fb < 1) fb = 1;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)fb), dim3(256), 0, s, wv);
+    hipLaunchKernelGGL(k_stage2, dim3(nb), dim3(kStage2Block), 0, s, wv, p.count, p.hbytes,
+                       p.n_bins, accumulate);
+    st = check_hip(hipGetLastError(), "stage-2 launch");
+    if (st != SINET_OK) return st;
+    // far sessions: labels are already stored, do not store them twice
+    FarList far{w.farlist, w.farcount, w.farbits};
+    PassParams q = p;
+    q.label_out = nullptr;
+    q.src_inst = nullptr;
+    q.dst_inst = nullptr;
+    q.dropped = nullptr;
+    return launch_k_pass(q, kind, H_ATOMIC, false, far, 0, s);
+}
+
+// ---- per-device pool for the stream-ordered workspace ------------------------
+static hipMemPool_t device_pool(int dev) {
+    static std::mutex mu;
+    static std::map<int, hipMemPool_t> pools;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    hipMemPoolProps props;
+    memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) pool = nullptr;
+    if (pool) {
+        uint64_t thr = ~0ull;  // keep freed blocks for reuse
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    pools[dev] = pool;
+    return pool;
+}
+
+sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+    hipMemPool_t pool = device_pool(dev);
+    e = pool ? hipMallocFromPoolAsync(ptr, bytes, pool, s) : hipMallocAsync(ptr, bytes, s);
+    return check_hip(e, "workspace allocation");
+}
+
+sinet_status ws_free(void* ptr, hipStream_t s) {
+    return check_hip(hipFreeAsync(ptr, s), "workspace free");
+}
+
+// Histogram strategy for a window: small windows are privatised in LDS.
+int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n) {
+    const size_t priv = 12ull * 4 * n_bins;
+    const size_t tab = kind == KK_LABEL_IN ? 0 : t.lds_bytes;
+    if (n_bins <= 2048 && priv + tab + 64 <= 96 * 1024) return H_PRIVATE;
+    (void)n;
+    return 3;  // partitioned
+}
+
+sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s) {
+    const uint32_t kind = (mode & PASS_LABEL_IN) ? (uint32_t)KK_LABEL_IN : p.t.kind;
+    if (p.n == 0) return SINET_OK;
+    const int strat = hist_strategy(p.t, kind, p.n_bins, p.n);
+    if (strat == H_PRIVATE) {
+        sinet_status st = SINET_OK;
+        if (!accumulate) {
+            st = launch_zero(p.count, 4ull * p.n_bins, s);
+            if (st == SINET_OK) st = launch_zero(p.hbytes, 4ull * p.n_bins, s);
+            if (st != SINET_OK) return st;
+        }
+        FarList none{};
+        return launch_k_pass(p, kind, H_PRIVATE, vector_ok(p, kind, true), none,
+                             12ull * 4 * p.n_bins + 8, s);
+    }
+    // partitioned: pieces of at most kMaxPiece sessions (32-bit slot indices)
+    int acc = accumulate;
+    for (uint64_t lo = 0; lo < p.n; lo += kMaxPiece) {
+        PassParams q = p;
+        const uint64_t len = p.n - lo < kMaxPiece ? p.n - lo : kMaxPiece;
+        q.n = len;
+        auto adv32 = [&](const uint32_t* a) { return a ? a + lo : a; };
+        q.ts = adv32(p.ts);
+        q.src = adv32(p.src);
+        q.dst = adv32(p.dst);
+        q.bytes = p.bytes ? p.bytes + lo : nullptr;
+        q.label_in = p.label_in ? p.label_in + lo : nullptr;
+        q.label_out = p.label_out ? p.label_out + lo : nullptr;
+        q.src_inst = p.src_inst ? p.src_inst + lo : nullptr;
+        q.dst_inst = p.dst_inst ? p.dst_inst + lo : nullptr;
+        void* ws = nullptr;
+        sinet_status st = ws_alloc(&ws, part_ws_bytes(len, p.n_bins), s);
+        if (st != SINET_OK) return st;
+        const PartWs w = part_ws_carve(ws, len, p.n_bins);
+        st = run_partitioned(q, kind, w, acc, s);
+        sinet_status st2 = ws_free(ws, s);
+        if (st != SINET_OK) return st;
+        if (st2 != SINET_OK) return st2;
+        acc = 1;
+    }
+    return SINET_OK;
 }
 
 }  // namespace sinet

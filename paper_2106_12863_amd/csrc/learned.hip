@@ -20,6 +20,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "sinet_device.h"
@@ -132,20 +133,108 @@ sinet_status measure_err(const DevTable& t, bool mlp, hipStream_t s, uint32_t* e
     return SINET_OK;
 }
 
-sinet_status train_pla(sinet_table* t, uint32_t S, hipStream_t s, sinet_train_report* r) {
+// Segment directory of a PLA: for each radix bucket r (the top radix_bits
+// address bits) the last segment whose knot is <= r's first address, plus a
+// final entry S - 1.  The segment of an address a in bucket r is then among
+// dir[r] .. dir[r + 1].  Stored as 16-bit entries, two per word.
+hipError_t upload_radix(sinet_table* t, const std::vector<uint32_t>& knots) {
+    const uint32_t bits = t->dev.radix_bits;
+    const uint32_t nb = 1u << bits;
+    std::vector<uint32_t> words(radix_words(bits), 0);
+    uint32_t s = 0;
+    const uint32_t S = (uint32_t)knots.size();
+    for (uint32_t r = 0; r <= nb; ++r) {
+        uint32_t e;
+        if (r == nb) {
+            e = S - 1;
+        } else {
+            const uint64_t first = (uint64_t)r << (32 - bits);
+            while (s + 1 < S && knots[s + 1] <= first) ++s;
+            e = s;
+        }
+        words[r >> 1] |= (e & 0xFFFFu) << ((r & 1) * 16);
+    }
+    return hipMemcpy((void*)t->dev.radix, words.data(), 4 * words.size(), hipMemcpyHostToDevice);
+}
+
+// Greedy error-bounded segmentation ("shrinking cone"): a segment's line
+// passes through its first boundary (B[j0], j0) and keeps the interval of
+// slopes that predict every later interval j of the segment within +-E at
+// both of its ends, B[j] and B[j+1] - 1; when the interval of slopes
+// empties, the next segment starts.  Slopes are >= 0 (the middle of the
+// feasible interval), so predictions stay monotone inside a segment.
+static void cone_segments(const std::vector<uint32_t>& B, double E, std::vector<uint32_t>& knot,
+                          std::vector<float>& c, std::vector<float>& g) {
+    knot.clear();
+    c.clear();
+    g.clear();
+    const size_t m = B.size();
+    auto end_of = [&](size_t j) { return j + 1 < m ? (double)B[j + 1] - 1.0 : 4294967295.0; };
+    size_t j0 = 0;
+    while (j0 < m) {
+        const double x0 = B[j0], y0 = (double)j0;
+        double lo = 0.0, hi = 1e300;
+        const double e0 = end_of(j0) - x0;  // the first interval's own end
+        if (e0 > 0) hi = E / e0;
+        size_t j = j0 + 1;
+        for (; j < m; ++j) {
+            const double dx = (double)B[j] - x0;
+            const double ex = end_of(j) - x0;
+            const double nlo = std::max(lo, ((double)j - E - y0) / dx);
+            const double nhi = std::min(hi, ((double)j + E - y0) / ex);
+            if (nlo > nhi) break;
+            lo = nlo;
+            hi = nhi;
+        }
+        double slope = hi < 1e299 ? 0.5 * (lo + hi) : 0.0;
+        if (!(slope >= 0.0)) slope = 0.0;
+        knot.push_back(B[j0]);
+        c.push_back((float)y0);
+        g.push_back((float)slope);
+        j0 = j;
+    }
+}
+
+sinet_status train_pla(sinet_table* t, uint32_t S, uint32_t E, uint32_t max_segments, hipStream_t s,
+                       sinet_train_report* r) {
     DevTable& d = t->dev;
-    if (S > d.m) S = d.m;
-    if (S == 0) S = 1;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, s);
-    hipLaunchKernelGGL(k_pla_fit, dim3(S), dim3(256), 0, s, d.B, d.m, S, (uint32_t*)d.knot,
-                       (float*)d.pla_c, (float*)d.pla_g);
-    hipError_t e = hipGetLastError();
+    std::vector<uint32_t> knots;
+    hipError_t e = hipSuccess;
+    if (S) {
+        // equal-count segments, least-squares lines fitted on the GPU
+        if (S > d.m) S = d.m;
+        if (S > max_segments) S = max_segments;
+        hipLaunchKernelGGL(k_pla_fit, dim3(S), dim3(256), 0, s, d.B, d.m, S, (uint32_t*)d.knot,
+                           (float*)d.pla_c, (float*)d.pla_g);
+        e = hipGetLastError();
+        knots.resize(S);
+        for (uint32_t k = 0; k < S; ++k) knots[k] = t->B[(uint64_t)k * d.m / S];
+    } else {
+        // error-bounded segmentation; the bound grows until the segments fit
+        std::vector<float> c, g;
+        double target = E ? (double)E : 8.0;
+        for (;;) {
+            cone_segments(t->B, target, knots, c, g);
+            if (knots.size() <= max_segments) break;
+            target *= 2;
+        }
+        S = (uint32_t)knots.size();
+        e = hipMemcpyAsync((void*)d.knot, knots.data(), 4ull * S, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void*)d.pla_c, c.data(), 4ull * S, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void*)d.pla_g, g.data(), 4ull * S, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
     (void)hipEventRecord(e1, s);
-    if (e != hipSuccess) return check_hip(e, "PLA fit launch");
+    if (e != hipSuccess) return check_hip(e, "PLA fit");
     d.segments = S;
+    e = upload_radix(t, knots);
+    if (e != hipSuccess) return check_hip(e, "PLA directory upload");
     uint32_t err = 0;
     sinet_status st = measure_err(d, false, s, &err);
     if (st != SINET_OK) return st;

@@ -26,12 +26,18 @@ __device__ __forceinline__ int clamp_pos(float pred, uint32_t m) {
     return (int)rintf(pred);
 }
 
-// PLA prediction: c[s] + g[s] * (a - knot[s]) in float32, round to nearest.
+// PLA line of one segment: c + g * (a - knot) in float32, round to nearest,
+// no contraction (the error bound is measured with exactly this arithmetic).
+__device__ __forceinline__ float pla_eval(uint32_t knot, float c, float g, uint32_t a) {
+    const float d = __uint2float_rn(a - knot);
+    return __fadd_rn(c, __fmul_rn(g, d));
+}
+
+// PLA prediction with the segment found by a full search over the knots.
 __device__ __forceinline__ float pla_predict(const uint32_t* knot, const float* c, const float* g,
                                              uint32_t S, uint32_t a) {
-    uint32_t s = upper_last(knot, S, a);
-    float d = __uint2float_rn(a - knot[s]);
-    return __fadd_rn(c[s], __fmul_rn(g[s], d));
+    const uint32_t s = upper_last(knot, S, a);
+    return pla_eval(knot[s], c[s], g[s], a);
 }
 
 // MLP prediction: m * (b2 + sum_k w2_k relu(w1_k x + b1_k)), x = a / 2^32.

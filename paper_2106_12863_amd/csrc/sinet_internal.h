@@ -41,7 +41,19 @@ struct DevTable {
     const uint32_t* knot;       // [segments]
     const float* pla_c;         // [segments]
     const float* pla_g;         // [segments]
+    const uint32_t* radix;      // PLA: first segment per radix bucket, u16 pairs
+    uint32_t radix_bits;
+    uint32_t filter_lds;        // 1: /16 filter staged in LDS and used
+    const uint32_t* filter;     // [kFilterWords] 2-bit state per /16 block:
+                                // 0 all out, 1 all in, 2 cut by a boundary
     const float* mlp;           // [49]
+    // in/out index (label-only queries): word offsets inside io[]
+    const uint32_t* io;         // [io_words] or nullptr
+    uint32_t io_words;
+    uint32_t io_rank;           // u16 pairs: mixed blocks before each filter word
+    uint32_t io_start;          // u16 pairs: first boundary of each mixed block (M + 1)
+    uint32_t io_sbit;           // bits: membership at the start of each mixed block
+    uint32_t io_list;           // u16 pairs: boundary offsets inside mixed blocks
     uint32_t max_err;
     float m_f;                  // (float) m
     unsigned long long* fallbacks;  // device counter
@@ -50,10 +62,41 @@ struct DevTable {
     uint32_t lds_bytes;
 };
 
-struct Launch {
-    int grid;
-    int block;
-    size_t lds;
+constexpr uint32_t kFilterWords = 65536 / 16;  // 2 bits per /16 block
+constexpr uint32_t kPlaRadixBits = 14;
+constexpr uint32_t kInoutKind = 6;              // internal kind: label-only via the in/out index          // PLA segment directory: top 14 address bits
+__host__ __device__ constexpr uint32_t radix_words(uint32_t bits) {
+    return ((1u << bits) + 2) / 2;  // (2^bits + 1) u16 entries
+}
+
+// Partitioned histogram geometry.
+constexpr int kChunk = 4096;        // sessions per stage-1 chunk
+constexpr int kBlockBins = 1024;    // bins per stage-2 block (all four labels)
+constexpr int kWin = 64;            // blocks one chunk may touch without the far path
+constexpr int kBigSlots = 128;      // 64-bit byte counts a chunk can hold out of line
+
+// Device workspace of the partitioned histogram (carved from one allocation).
+struct PartWs {
+    uint32_t* rec;                  // [n_chunks * kChunk] 4-byte records
+    unsigned long long* big;        // [n_chunks * kBigSlots] out-of-line byte counts
+    uint4* dir;                     // [n_chunks * kWin] (block, first slot, count, -)
+    uint32_t* nd;                   // [n_chunks] directory entries per chunk
+    uint32_t* farbits;              // [n_chunks * kChunk / 32] far sessions (flagged chunks)
+    uint32_t* farlist;              // [n_chunks] chunks holding far sessions
+    uint32_t* farcount;             // [1]
+    uint32_t* seg_count;            // [n_blocks] directory entries per block
+    uint32_t* seg_off;              // [n_blocks + 1] exclusive scan of seg_count
+    uint2* segs;                    // [n_chunks * kWin] (first slot, count) grouped by block
+    uint32_t* scan_tiles;           // scan scratch
+    uint64_t n_chunks;
+    uint32_t n_blocks;
+    uint32_t vec;                   // 16-byte vector loads allowed
+};
+
+struct FarList {
+    const uint32_t* list;
+    const uint32_t* count;
+    const uint32_t* bits;
 };
 
 // Kernel-side parameters of one pass over a stream of sessions.
@@ -112,11 +155,22 @@ enum PassMode : uint32_t {
 };
 sinet_status launch_pass(const PassParams& p, uint32_t mode, hipStream_t s);
 sinet_status launch_zero(unsigned long long* p, uint64_t n_words, hipStream_t s);
+// histogram passes (labels computed or given) with the strategy chosen per window
+sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s);
+size_t part_ws_bytes(uint64_t n, uint32_t n_bins);
+PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins);
+sinet_status run_partitioned(const PassParams& p, uint32_t kind, const PartWs& w, int accumulate,
+                             hipStream_t s);
+int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n);
+sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s);
+sinet_status ws_free(void* ptr, hipStream_t s);
 uint32_t device_cu_count();
 uint64_t div_magic(uint32_t width);
 
 // learned.hip
-sinet_status train_pla(sinet_table* t, uint32_t segments, hipStream_t s, sinet_train_report* r);
+sinet_status train_pla(sinet_table* t, uint32_t segments, uint32_t target_err, uint32_t max_segments,
+                       hipStream_t s, sinet_train_report* r);
+hipError_t upload_radix(sinet_table* t, const std::vector<uint32_t>& knots);
 sinet_status train_mlp(sinet_table* t, const sinet_train_params* p, hipStream_t s,
                        sinet_train_report* r);
 sinet_status measure_err(const DevTable& t, bool mlp, hipStream_t s, uint32_t* err);

@@ -69,14 +69,16 @@ def test_device_generator_equals_host(sinet, torch):
 
 
 # ---------------------------------------------------------- fused pipeline
-@pytest.mark.parametrize("kind", ["scan", "bsearch", "trie", "auto"])
-def test_pipeline_tiny_config_all_kinds(sinet, torch, kind):
+@pytest.mark.parametrize("kind,inout", [("scan", False), ("bsearch", True), ("bsearch", False),
+                                        ("trie", True), ("trie", False), ("auto", True)])
+def test_pipeline_tiny_config_all_kinds(sinet, torch, kind, inout):
     wl = sinetgen.config(1)
-    _say("pipeline tiny", kind, wl.n)
+    _say("pipeline tiny", kind, inout, wl.n)
     s = sinetgen.sessions(wl)
     ts, src, dst, nb = _up(sinet, s)
     w = wl.window
-    tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
+    tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=inout)
+    assert tab.info().inout_index == (1 if inout and kind != "auto" else 0) or kind == "auto"
     lab, out = sinet.pipeline(tab, ts, src, dst, nb, w.t0, w.width, w.n_bins)
     torch.cuda.synchronize()
     elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"], s["bytes"],
@@ -108,11 +110,14 @@ def test_pipeline_day_shape_full_bins(sinet, torch):
     s = sinetgen.sessions(wl)
     ts, src, dst, nb = _up(sinet, s)
     w = wl.window
-    for kind in ("bsearch", "trie"):
-        tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
+    for kind, inout in (("bsearch", True), ("bsearch", False), ("trie", False), ("pla", False)):
+        tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=inout)
+        if kind == "pla":
+            tab.train()
+        assert tab.info().inout_index == int(inout)
         lab, out = sinet.pipeline(tab, ts, src, dst, nb, w.t0, w.width, w.n_bins)
         torch.cuda.synchronize()
-        if kind == "bsearch":
+        if kind == "bsearch" and inout:
             elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"],
                                                s["bytes"], w.t0, w.width, w.n_bins)
         assert np.array_equal(lab.cpu().numpy(), elab), kind
@@ -267,13 +272,19 @@ def test_intervals_and_positions(sinet, torch, cfg):
         tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
         gB, gown = tab.intervals()
         assert np.array_equal(gB, B) and np.array_equal(gown, own), kind
-        if kind in ("pla", "mlp"):
-            tab.train(steps=300)
-        pos = tab.position(qd)
-        torch.cuda.synchronize()
-        assert np.array_equal(sinet.to_host_u32(pos).astype(np.int64), expect), kind
-        if kind == "pla":
-            assert tab.info().fallbacks == 0
+        modes = [{}]
+        if kind == "mlp":
+            modes = [{"steps": 300}]
+        if kind == "pla":   # error-bounded segmentation, and 256 least-squares segments
+            modes = [{}, {"target_err": 2}, {"segments": 256}]
+        for mode in modes:
+            if kind in ("pla", "mlp"):
+                tab.train(**mode)
+            pos = tab.position(qd)
+            torch.cuda.synchronize()
+            assert np.array_equal(sinet.to_host_u32(pos).astype(np.int64), expect), (kind, mode)
+            if kind == "pla":
+                assert tab.info().fallbacks == 0, mode
 
 
 # ---------------------------------------------------------- full-size day
@@ -345,13 +356,26 @@ def test_mlp_gradients_vs_oracle(sinet, torch):
         assert abs(float(loss.item()) - eloss) <= 1e-5 * eloss + 1e-12
 
 
-@pytest.mark.parametrize("kind", ["pla", "mlp"])
-def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind):
+@pytest.mark.parametrize("kind,inout", [("pla", False), ("mlp", False), ("pla", True),
+                                        ("bsearch", False), ("trie", False)])
+def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, inout):
+    """The 200,000-prefix clustered table: labels and histograms of every
+    kind, with the kind's own search (in/out index off) and with the index."""
     wl = sinetgen.config(4, n=2_000_000)
-    _say("learned", kind)
+    _say("large table", kind, inout)
     s = sinetgen.sessions(wl, start=0, stop=wl.n)
     ts, src, dst, nb = _up(sinet, s)
-    tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
+    tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=inout)
+    assert tab.info().inout_index == int(inout)
+    if kind not in ("pla", "mlp"):
+        w = wl.window
+        lab, out = sinet.pipeline(tab, ts, src, dst, nb, w.t0, w.width, w.n_bins)
+        torch.cuda.synchronize()
+        elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"],
+                                           s["bytes"], w.t0, w.width, w.n_bins)
+        assert np.array_equal(lab.cpu().numpy(), elab)
+        _cmp_hist(sinet, out, (ec, eb, ed))
+        return
     rep = tab.train(steps=1500)
     info = tab.info()
     assert info.trained == 1 and info.max_err == rep.max_err
