@@ -1,15 +1,25 @@
 """Benchmark: sessions/s of fused discrimination + millisecond histogram on one
-MI355X, with the HBM roofline of the dominant kernel and the CPU oracle
-timed beside it.
+MI355X, with the HBM roofline of the timed step and the CPU oracle timed
+beside it.
 
-One step = one sinet_pipeline call over the whole resident day: clear the
-4 x n_bins histogram, then one pass that reads every session's ts/src/dst/
-bytes, looks both addresses up in the prefix table, writes the label and
-merges (1, bytes) into its (label, 1-ms bin).  Inputs are synthetic (seeded
-generator, written straight into HBM) with the paper's day shape.
+One step = one pass of the whole hot path over the resident day: every
+session's ts/src/dst/bytes read once, both addresses classified against the
+prefix table, the label written, and (1, bytes) merged into its (label, 1-ms
+bin); the 4 x 86.4 M-bin histogram is fully written (no separate clear).
+Inputs are synthetic (seeded generator writing straight into HBM) with the
+paper's day shape.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|4|5]
-                    [--lookup bsearch|trie|pla|mlp|auto] [--no-cpu]
+Forms timed on the same resident day (the first is the headline value):
+  plain        bsearch table, labels from its in/out index (LDS)
+  bsearch      plain binary search over the interval boundaries (no index)
+  trie         16-8-8 multibit trie (no index)
+  pla          learned: error-bounded piecewise-linear model + bounded search
+  mlp          learned: 1-16-1 ReLU MLP + bounded search
+  batched      the day cut into time-ordered streams, one graph launch
+               (table with the learned PLA and the in/out index)
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5|4|2|3]
+                    [--forms plain,bsearch,...] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -26,6 +36,7 @@ METRIC = "sessions/sec classify+histogram on 1 GPU, % HBM roofline; learned vs p
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SESSION = 21   # ts 4 + src 4 + dst 4 + bytes 8 read, label 1 written
 BYTES_PER_BIN = 64       # 4 labels x (count 8 + bytes 8) written once
+DEFAULT_FORMS = "plain,bsearch,trie,pla,mlp,batched"
 
 
 def log(*a):
@@ -35,20 +46,21 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=5)
     ap.add_argument("--n", type=int, default=0, help="override the session count")
-    ap.add_argument("--lookup", default="")
-    ap.add_argument("--compare", default="", help="comma list of extra lookups to time")
+    ap.add_argument("--forms", default="")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0)
+    ap.add_argument("--day-streams", type=int, default=24, help="streams of the batched day")
     return ap.parse_args()
 
 
 def time_calls(torch, fn, steps, warmup):
-    """Average device ms per call, HIP events on the stream the library uses
-    (torch's current stream), plus the host wall time of the whole loop."""
+    """Average and minimum device ms per call from HIP events recorded on the
+    stream the library launches on (torch's current stream), plus host wall
+    ms per call over the timed loop."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -67,8 +79,8 @@ def time_calls(torch, fn, steps, warmup):
 
 
 def cpu_baseline(wl, cols, sinet, sample: int):
-    """The C oracle (single thread) on a contiguous sample of the same day."""
-    import numpy as np
+    """The C oracle (single thread, per-length hash) on a contiguous sample of
+    the same day; generation and copies excluded."""
     import oracle
     n = min(sample, wl.n)
     i0 = (wl.n - n) // 2
@@ -80,8 +92,150 @@ def cpu_baseline(wl, cols, sinet, sample: int):
                     w.n_bins, mode="hash")
     dt = time.perf_counter() - t
     return {"value": n / dt, "unit": "sessions/s", "cores": 1, "kind": "oracle",
-            "sample": f"sessions [{i0}, {i0 + n}) of the same day, per-length-hash LPM, "
-                      f"full {w.n_bins}-bin x 4-label histogram cleared and filled; {dt:.1f} s"}
+            "sample": f"sessions [{i0}, {i0 + n}) of the same day ({n} sessions, {dt:.1f} s): "
+                      f"per-length-hash longest-prefix match over {wl.n_prefix} prefixes, "
+                      f"{w.n_bins}-bin x 4-label histogram cleared and filled"}
+
+
+def day_streams(sinet, wl, cols, tab, k, label, out):
+    """The day cut into k time-ordered index ranges: every range is its own
+    stream with the full-day window, so the batch adds into one histogram
+    would double-count; instead each stream gets its own slice of the day's
+    bins (its time range, padded by the jitter) and its own output."""
+    import torch
+    w = wl.window
+    per = (wl.n + k - 1) // k
+    streams, outs = [], []
+    import sinetgen
+    for i in range(k):
+        lo, hi = i * per, min(wl.n, (i + 1) * per)
+        if lo >= hi:
+            break
+        t_lo = int(sinetgen.ts_base(wl, [lo])[0]) - wl.jitter - 1
+        t_hi = int(sinetgen.ts_base(wl, [hi - 1])[0]) + wl.jitter + 1
+        t0 = max(w.t0, t_lo)
+        nb = min(w.n_bins, t_hi - t0 + 1)
+        o = sinet.new_hist(nb)
+        outs.append(o)
+        streams.append(sinet.BatchStream(tab, cols["ts"][lo:hi], cols["src"][lo:hi],
+                                         cols["dst"][lo:hi], cols["bytes"][lo:hi], t0, w.width,
+                                         nb, label=label[lo:hi], out=o))
+    return streams, outs
+
+
+def bench_day(args, torch, sinet, sinetgen, gg):
+    wl = sinetgen.config(args.config, n=args.n or None)
+    forms = (args.forms or (DEFAULT_FORMS if args.config in (4, 5) else "plain,bsearch,trie")).split(",")
+    log(f"config {args.config}: {wl.name} n={wl.n} prefixes={wl.n_prefix} forms={forms}")
+    cols = gg.alloc_and_fill(wl)
+    torch.cuda.synchronize()
+    w = wl.window
+    label = torch.empty(wl.n, dtype=torch.uint8, device="cuda")
+    out = sinet.new_hist(w.n_bins)
+    results = {}
+    for form in forms:
+        if form == "batched":
+            tab = sinet.Table(wl.pbase, wl.plen, kind="pla")
+            rep = tab.train()
+            streams, outs = day_streams(sinet, wl, cols, tab, args.day_streams, label, out)
+            tune = sinet.autotune(streams)
+            plan = sinet.BatchPlan(streams, tune=tune)
+            fn = plan.run
+        else:
+            kind = "bsearch" if form == "plain" else form
+            tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=(form == "plain"))
+            rep = tab.train() if kind in ("pla", "mlp") else None
+            fn = (lambda t=tab: sinet.pipeline(t, cols["ts"], cols["src"], cols["dst"],
+                                               cols["bytes"], w.t0, w.width, w.n_bins,
+                                               label=label, out=out))
+        ms, ms_min, wall = time_calls(torch, fn, args.steps, args.warmup)
+        info = tab.info()
+        results[form] = {"sessions_per_s": wl.n / (ms * 1e-3), "ms_per_step": ms, "ms_min": ms_min,
+                         "wall_ms": wall, "kind": sinet.KIND_NAMES[info.kind],
+                         "inout_index": bool(info.inout_index) and form in ("plain", "batched"),
+                         "m": int(info.m), "max_err": int(info.max_err),
+                         "segments": int(info.segments), "fallbacks": int(info.fallbacks),
+                         "train_ms": None if rep is None else round(rep.train_ms, 3)}
+        if form == "batched":
+            results[form]["tune"] = {"block": tune.block, "chunk": tune.chunk, "grid": tune.grid}
+            results[form]["streams"] = len(streams)
+            del plan, streams, outs
+        log(form, json.dumps(results[form]))
+        del tab
+    head = forms[0]
+    r = results[head]
+    alg_bytes = BYTES_PER_SESSION * wl.n + BYTES_PER_BIN * w.n_bins
+    achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": r["sessions_per_s"], "unit": "sessions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32,u64",
+        "data": "synthetic (seeded SINET-shaped day generated in HBM)",
+        "config": {"workload": wl.name, "n_sessions": wl.n, "n_prefix": wl.n_prefix,
+                   "n_bins": w.n_bins, "bin_ms": w.width, "form": head,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one sinet_pipeline step: k_stage1 (lookup + label + partition) "
+                               "+ segment index + k_stage2 (block reduce, one write per bin)",
+                     "alg_bytes_per_launch": alg_bytes, "launch_ms": r["ms_per_step"]},
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("wall_ms",)}
+                  for k, v in results.items()},
+    }
+    for k, v in results.items():
+        line["forms"][k]["hbm_frac"] = alg_bytes / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if not args.no_cpu:
+        sample = args.cpu_sample or (20_000_000 if wl.n_prefix <= 4096 else 8_000_000)
+        line["cpu_baseline"] = cpu_baseline(wl, cols, sinet, sample)
+    return line
+
+
+def bench_batch(args, torch, sinet, sinetgen, gg):
+    """Config 3: 64 uneven streams, each with its own table, window and bin
+    width: one autotuned graph launch against per-stream pipeline calls."""
+    streams_wl = sinetgen.batch_streams()
+    log(f"config 3: {len(streams_wl)} streams, {sum(s.n for s in streams_wl)} sessions")
+    built = []
+    for wl in streams_wl:
+        cols = gg.alloc_and_fill(wl)
+        tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch")
+        lab = torch.empty(wl.n, dtype=torch.uint8, device="cuda")
+        out = sinet.new_hist(wl.window.n_bins)
+        built.append((wl, cols, tab, lab, out))
+    torch.cuda.synchronize()
+    bs = [sinet.BatchStream(tab, c["ts"], c["src"], c["dst"], c["bytes"], wl.window.t0,
+                            wl.window.width, wl.window.n_bins, label=lab, out=out)
+          for wl, c, tab, lab, out in built]
+    tune = sinet.autotune(bs)
+    plan = sinet.BatchPlan(bs, tune=tune)
+
+    def per_stream():
+        for wl, c, tab, lab, out in built:
+            sinet.pipeline(tab, c["ts"], c["src"], c["dst"], c["bytes"], wl.window.t0,
+                           wl.window.width, wl.window.n_bins, label=lab, out=out)
+
+    n = sum(wl.n for wl in streams_wl)
+    bins = sum(wl.window.n_bins for wl in streams_wl)
+    ms_b, min_b, _ = time_calls(torch, plan.run, args.steps, args.warmup)
+    ms_p, min_p, _ = time_calls(torch, per_stream, args.steps, args.warmup)
+    alg_bytes = BYTES_PER_SESSION * n + BYTES_PER_BIN * bins
+    achieved = alg_bytes / (ms_b * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": n / (ms_b * 1e-3), "unit": "sessions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32,u64",
+        "data": "synthetic (seeded uneven streams generated in HBM)",
+        "config": {"workload": f"batch-{len(streams_wl)}streams-{n}sessions", "n_sessions": n,
+                   "n_bins_total": bins, "form": "batched", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one batch graph launch", "alg_bytes_per_launch": alg_bytes,
+                     "launch_ms": ms_b},
+        "forms": {"batched": {"ms_per_step": ms_b, "ms_min": min_b,
+                              "tune": {"block": tune.block, "chunk": tune.chunk, "grid": tune.grid}},
+                  "per_stream_calls": {"ms_per_step": ms_p, "ms_min": min_p,
+                                       "sessions_per_s": n / (ms_p * 1e-3)}},
+    }
 
 
 def main():
@@ -93,64 +247,10 @@ def main():
     import paper_2106_12863_amd as sinet
     import sinetgen
     import sinetgen.gpu as gg
-
-    wl = sinetgen.config(args.config, n=args.n or None)
-    lookup = args.lookup or ("pla" if args.config in (4, 5) else "bsearch")
-    log(f"config {args.config}: {wl.name} n={wl.n} prefixes={wl.n_prefix} lookup={lookup}")
-    cols = gg.alloc_and_fill(wl)
-    torch.cuda.synchronize()
-    w = wl.window
-    label = torch.empty(wl.n, dtype=torch.uint8, device="cuda")
-    out = sinet.new_hist(w.n_bins)
-
-    def make_table(kind):
-        tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
-        rep = tab.train() if kind in ("pla", "mlp") else None
-        return tab, rep
-
-    def step_fn(tab, acc=False):
-        return lambda: sinet.pipeline(tab, cols["ts"], cols["src"], cols["dst"], cols["bytes"],
-                                      w.t0, w.width, w.n_bins, label=label, out=out,
-                                      accumulate=acc)
-
-    results = {}
-    kinds = [lookup] + [k for k in args.compare.split(",") if k and k != lookup]
-    for kind in kinds:
-        tab, rep = make_table(kind)
-        info = tab.info()
-        ms, ms_min, wall = time_calls(torch, step_fn(tab), args.steps, args.warmup)
-        info = tab.info()
-        results[kind] = {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall,
-                         "sessions_per_s": wl.n / (ms * 1e-3), "m": int(info.m),
-                         "max_err": int(info.max_err), "segments": int(info.segments),
-                         "fallbacks": int(info.fallbacks),
-                         "train_ms": None if rep is None else rep.train_ms}
-        log(kind, json.dumps(results[kind]))
-        del tab
-    r = results[lookup]
-    alg_bytes = BYTES_PER_SESSION * wl.n + BYTES_PER_BIN * w.n_bins
-    achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
-    line = {
-        "metric": METRIC, "value": r["sessions_per_s"], "unit": "sessions/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32,u64",
-        "data": "synthetic (seeded SINET-shaped day generated in HBM)",
-        "config": {"workload": wl.name, "n_sessions": wl.n, "n_prefix": wl.n_prefix,
-                   "n_bins": w.n_bins, "bin_ms": w.width, "lookup": lookup,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sinet_pipeline step: k_stage1 (lookup+label+partition) + "
-                               "segment index + k_stage2 (block reduce, one write per bin)",
-                     "alg_bytes_per_launch": alg_bytes, "launch_ms": r["ms_per_step"]},
-        "lookups": {k: {"sessions_per_s": v["sessions_per_s"], "ms_per_step": v["ms_per_step"],
-                        "max_err": v["max_err"], "segments": v["segments"],
-                        "fallbacks": v["fallbacks"]}
-                    for k, v in results.items()},
-    }
-    if not args.no_cpu:
-        sample = args.cpu_sample or 20_000_000
-        line["cpu_baseline"] = cpu_baseline(wl, cols, sinet, sample)
+    if args.config == 3:
+        line = bench_batch(args, torch, sinet, sinetgen, gg)
+    else:
+        line = bench_day(args, torch, sinet, sinetgen, gg)
     print(json.dumps(line), flush=True)
 
 

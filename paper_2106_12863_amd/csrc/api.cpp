@@ -222,7 +222,7 @@ static sinet_status check_device(const sinet_table* t) {
     return SINET_OK;
 }
 
-static sinet_status check_usable(const sinet_table* t) {
+sinet_status check_usable(const sinet_table* t) {
     if (!t) return fail(SINET_ERR_INVALID_ARG, "table is NULL");
     if ((t->kind == SINET_LOOKUP_LEARNED_PLA || t->kind == SINET_LOOKUP_LEARNED_MLP) && !t->trained)
         return fail(SINET_ERR_INVALID_ARG, "learned table used before sinet_table_train");
@@ -231,7 +231,7 @@ static sinet_status check_usable(const sinet_table* t) {
 
 // The device view a pass uses: label-only passes of a table with an in/out
 // index run the index kind (LDS holds the index alone).
-static DevTable label_view(const sinet_table* t, bool label_only) {
+DevTable label_view(const sinet_table* t, bool label_only) {
     DevTable d = t->dev;
     if (label_only && d.io) {
         d.kind = kInoutKind;
@@ -240,7 +240,7 @@ static DevTable label_view(const sinet_table* t, bool label_only) {
     return d;
 }
 
-static sinet_status check_window(const sinet_window* w) {
+sinet_status check_window(const sinet_window* w) {
     if (!w) return fail(SINET_ERR_INVALID_ARG, "window is NULL");
     if (w->width_ms == 0) return fail(SINET_ERR_INVALID_ARG, "width_ms is 0");
     if (w->n_bins == 0) return fail(SINET_ERR_INVALID_ARG, "n_bins is 0");

@@ -51,7 +51,6 @@ enum KernelKind : uint32_t {
 
 constexpr int kXcds = 8;
 constexpr int kMaxBlock = 1024;
-constexpr int kStage1Block = kChunk / 4;  // 4 sessions per lane
 constexpr int kStage2Block = 256;
 constexpr int kSegBatch = kStage2Block;    // segments staged per stage-2 round
 constexpr int kRecUnroll = 8;              // independent record loads per stage-2 lane
@@ -658,14 +657,144 @@ __device__ __forceinline__ void load4(const PassParams& p, uint64_t i, Raw4& r) 
     r.b23 = *reinterpret_cast<const ulonglong2*>(p.bytes + i + 2);
 }
 
+// LDS scratch of one stage-1 workgroup.
+struct Stage1Shared {
+    uint32_t cnt[kWin];
+    uint32_t base[kWin];
+    uint32_t far[kChunk / 32];
+    uint32_t wmin[kStage1Block / 64];
+    uint32_t nbig, nfar, bmin;
+};
+
+// Stage 1 on one chunk.  c is the chunk within the stream (sessions
+// c * kChunk + ...), g its index in the workspace (slots, directory, far
+// bits) and b0 the workspace index of the stream's first block.
+template <uint32_t KIND>
+__device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& w, const LdsView& v,
+                                             Stage1Shared& sh, uint64_t c, uint64_t g, uint32_t b0,
+                                             const Raw4& cur, bool full, Dropped& d) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t i0 = c * kChunk + (uint64_t)tid * 4;
+    uint32_t lab[4], ts[4], bin[4];
+    unsigned long long by[4];
+    bool inw[4];
+    if (full) {
+        labels4_from<KIND>(p, v, i0, cur.src, cur.dst, cur.l4, lab);
+        ts[0] = cur.ts.x; ts[1] = cur.ts.y; ts[2] = cur.ts.z; ts[3] = cur.ts.w;
+        by[0] = cur.b01.x; by[1] = cur.b01.y; by[2] = cur.b23.x; by[3] = cur.b23.y;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) inw[k] = in_window(p, ts[k], bin[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = i0 + k;
+            inw[k] = false;
+            lab[k] = 0;
+            ts[k] = 0;
+            by[k] = 0;
+            bin[k] = 0;
+            if (i < p.n) {
+                if constexpr (KIND == KK_LABEL_IN) {
+                    lab[k] = p.label_in[i] & 3u;
+                } else {
+                    lab[k] = label1<KIND>(p, v, i);
+                }
+                ts[k] = p.ts[i];
+                by[k] = p.bytes[i];
+                inw[k] = in_window(p, ts[k], bin[k]);
+            }
+        }
+    }
+    uint32_t blk[4];
+    uint32_t mymin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        blk[k] = bin[k] / kBlockBins;
+        if (inw[k]) mymin = min(mymin, blk[k]);
+        else if (i0 + k < p.n) d.add(lab[k], by[k]);
+    }
+    mymin = wave_min(mymin);
+    if ((tid & 63) == 0) sh.wmin[tid >> 6] = mymin;
+    if (tid < kWin) sh.cnt[tid] = 0;
+    for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block) sh.far[k] = 0;
+    if (tid == 0) {
+        sh.nbig = 0;
+        sh.nfar = 0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        uint32_t m = tid < kStage1Block / 64 ? sh.wmin[tid] : 0xFFFFFFFFu;
+        m = wave_min(m);
+        if (tid == 0) sh.bmin = m;
+    }
+    __syncthreads();
+    const uint32_t bmin = sh.bmin;
+    uint32_t rank[4], bigi[4];
+    bool loc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t r = blk[k] - bmin;
+        loc[k] = inw[k] && r < kWin && by[k] < (1ull << 52);
+        bigi[k] = 0xFFFFFFFFu;
+        if (loc[k] && by[k] >= kSmallMax) {
+            bigi[k] = atomicAdd(&sh.nbig, 1u);
+            if (bigi[k] >= kBigSlots) loc[k] = false;
+        }
+        rank[k] = loc[k] ? atomicAdd(&sh.cnt[r], 1u) : 0u;
+        if (inw[k] && !loc[k]) {
+            const uint32_t sidx = tid * 4 + k;
+            atomicOr(&sh.far[sidx >> 5], 1u << (sidx & 31));
+            atomicAdd(&sh.nfar, 1u);
+        }
+    }
+    __syncthreads();
+    if (tid < 64) {  // exclusive scan of the kWin (= 64) block counts, one wave
+        const uint32_t x = sh.cnt[tid];
+        uint32_t inc = x;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
+            if ((int)tid >= o) inc += y;
+        }
+        sh.base[tid] = inc - x;
+        // directory entry of every touched block
+        const bool nz = x != 0;
+        const unsigned long long m = __ballot(nz);
+        const uint32_t e = __popcll(m & ((1ull << tid) - 1ull));
+        if (nz) {
+            const uint32_t b = b0 + bmin + tid;
+            w.dir[g * kWin + e] = make_uint4(b, (uint32_t)(g * kChunk) + (inc - x), x, 0u);
+            atomicAdd(w.seg_count + b, 1u);
+        }
+        if (tid == 0) w.nd[g] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    const uint64_t slot0 = g * kChunk;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!loc[k]) continue;
+        const uint32_t r = blk[k] - bmin;
+        const uint32_t off = bin[k] - blk[k] * kBlockBins;
+        uint32_t rec = (lab[k] << 30) | (off << 20);
+        if (bigi[k] != 0xFFFFFFFFu) {
+            rec |= (1u << 19) | bigi[k];
+            w.big[g * kBigSlots + bigi[k]] = by[k];
+        } else {
+            rec |= (uint32_t)by[k];
+        }
+        w.rec[slot0 + sh.base[r] + rank[k]] = rec;
+    }
+    if (sh.nfar) {
+        for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block)
+            w.farbits[g * (kChunk / 32) + k] = sh.far[k];
+        if (tid == 0) w.farlist[atomicAdd(w.farcount, 1u)] = (uint32_t)g;
+    }
+    __syncthreads();
+}
+
 template <uint32_t KIND>
 __global__ void __launch_bounds__(kStage1Block) k_stage1(PassParams p, PartWs w) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t s_cnt[kWin];
-    __shared__ uint32_t s_base[kWin];
-    __shared__ uint32_t s_far[kChunk / 32];
-    __shared__ uint32_t s_wmin[kStage1Block / 64];
-    __shared__ uint32_t s_nbig, s_nfar, s_bmin;
+    __shared__ Stage1Shared sh;
     uint32_t used = 0;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
     Dropped d{};
@@ -679,122 +808,8 @@ __global__ void __launch_bounds__(kStage1Block) k_stage1(PassParams p, PartWs w)
     for (; c < n_chunks; c += gridDim.x) {
         const uint64_t cn = c + gridDim.x;
         if (cn < n_chunks && full(cn)) load4<KIND>(p, cn * kChunk + (uint64_t)tid * 4, nxt);
-        const uint64_t i0 = c * kChunk + (uint64_t)tid * 4;
-        uint32_t lab[4], ts[4], bin[4];
-        unsigned long long by[4];
-        bool inw[4];
-        if (full(c)) {
-            labels4_from<KIND>(p, v, i0, cur.src, cur.dst, cur.l4, lab);
-            ts[0] = cur.ts.x; ts[1] = cur.ts.y; ts[2] = cur.ts.z; ts[3] = cur.ts.w;
-            by[0] = cur.b01.x; by[1] = cur.b01.y; by[2] = cur.b23.x; by[3] = cur.b23.y;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) inw[k] = in_window(p, ts[k], bin[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint64_t i = i0 + k;
-                inw[k] = false;
-                lab[k] = 0;
-                ts[k] = 0;
-                by[k] = 0;
-                bin[k] = 0;
-                if (i < p.n) {
-                    if constexpr (KIND == KK_LABEL_IN) {
-                        lab[k] = p.label_in[i] & 3u;
-                    } else {
-                        lab[k] = label1<KIND>(p, v, i);
-                    }
-                    ts[k] = p.ts[i];
-                    by[k] = p.bytes[i];
-                    inw[k] = in_window(p, ts[k], bin[k]);
-                }
-            }
-        }
+        stage1_chunk<KIND>(p, w, v, sh, c, c, 0u, cur, full(c), d);
         cur = nxt;
-        uint32_t blk[4];
-        uint32_t mymin = 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            blk[k] = bin[k] / kBlockBins;
-            if (inw[k]) mymin = min(mymin, blk[k]);
-            else if (i0 + k < p.n) d.add(lab[k], by[k]);
-        }
-        mymin = wave_min(mymin);
-        if ((tid & 63) == 0) s_wmin[tid >> 6] = mymin;
-        if (tid < kWin) s_cnt[tid] = 0;
-        for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block) s_far[k] = 0;
-        if (tid == 0) {
-            s_nbig = 0;
-            s_nfar = 0;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            uint32_t m = tid < kStage1Block / 64 ? s_wmin[tid] : 0xFFFFFFFFu;
-            m = wave_min(m);
-            if (tid == 0) s_bmin = m;
-        }
-        __syncthreads();
-        const uint32_t bmin = s_bmin;
-        uint32_t rank[4], bigi[4];
-        bool loc[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t r = blk[k] - bmin;
-            loc[k] = inw[k] && r < kWin && by[k] < (1ull << 52);
-            bigi[k] = 0xFFFFFFFFu;
-            if (loc[k] && by[k] >= kSmallMax) {
-                bigi[k] = atomicAdd(&s_nbig, 1u);
-                if (bigi[k] >= kBigSlots) loc[k] = false;
-            }
-            rank[k] = loc[k] ? atomicAdd(&s_cnt[r], 1u) : 0u;
-            if (inw[k] && !loc[k]) {
-                const uint32_t sidx = tid * 4 + k;
-                atomicOr(&s_far[sidx >> 5], 1u << (sidx & 31));
-                atomicAdd(&s_nfar, 1u);
-            }
-        }
-        __syncthreads();
-        if (tid < 64) {  // exclusive scan of the kWin (= 64) block counts, one wave
-            const uint32_t x = s_cnt[tid];
-            uint32_t inc = x;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
-                if ((int)tid >= o) inc += y;
-            }
-            s_base[tid] = inc - x;
-            // directory entry of every touched block
-            const bool nz = x != 0;
-            const unsigned long long m = __ballot(nz);
-            const uint32_t e = __popcll(m & ((1ull << tid) - 1ull));
-            if (nz) {
-                const uint32_t b = bmin + tid;
-                w.dir[c * kWin + e] = make_uint4(b, (uint32_t)(c * kChunk) + (inc - x), x, 0u);
-                atomicAdd(w.seg_count + b, 1u);
-            }
-            if (tid == 0) w.nd[c] = (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-        const uint64_t slot0 = c * kChunk;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (!loc[k]) continue;
-            const uint32_t r = blk[k] - bmin;
-            const uint32_t off = bin[k] - blk[k] * kBlockBins;
-            uint32_t rec = (lab[k] << 30) | (off << 20);
-            if (bigi[k] != 0xFFFFFFFFu) {
-                rec |= (1u << 19) | bigi[k];
-                w.big[c * kBigSlots + bigi[k]] = by[k];
-            } else {
-                rec |= (uint32_t)by[k];
-            }
-            w.rec[slot0 + s_base[r] + rank[k]] = rec;
-        }
-        if (s_nfar) {
-            for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block)
-                w.farbits[c * (kChunk / 32) + k] = s_far[k];
-            if (tid == 0) w.farlist[atomicAdd(w.farcount, 1u)] = (uint32_t)c;
-        }
-        __syncthreads();
     }
     d.flush(p.dropped);
 }
@@ -884,20 +899,29 @@ __global__ void k_fill(PartWs w) {
 // segments are taken kSegBatch at a time: their (first slot, count) pairs and
 // a prefix sum of the counts go to LDS, and every lane then walks the batch's
 // records by flat index, so all record loads of a batch are in flight at once.
-__global__ void __launch_bounds__(kStage2Block) k_stage2(PartWs w, unsigned long long* count,
-                                                        unsigned long long* hbytes, uint32_t n_bins,
-                                                        int accumulate) {
-    __shared__ unsigned long long s_b[4 * kBlockBins];
-    __shared__ uint32_t s_c[4 * kBlockBins];
-    __shared__ uint32_t s_start[kSegBatch];
-    __shared__ uint32_t s_pref[kSegBatch + 1];
-    __shared__ uint32_t s_w[kStage2Block / 64];
-    const uint32_t blk = blockIdx.x;
+struct Stage2Shared {
+    unsigned long long b[4 * kBlockBins];
+    uint32_t c[4 * kBlockBins];
+    uint32_t start[kSegBatch];
+    uint32_t pref[kSegBatch + 1];
+    uint32_t w[kStage2Block / 64];
+};
+
+// gblk: the block's index in the workspace; blk: its index in the stream.
+__device__ __forceinline__ void stage2_block(const PartWs& w, Stage2Shared& sh, uint32_t gblk,
+                                             uint32_t blk, unsigned long long* count,
+                                             unsigned long long* hbytes, uint32_t n_bins,
+                                             int accumulate) {
+    unsigned long long* s_b = sh.b;
+    uint32_t* s_c = sh.c;
+    uint32_t* s_start = sh.start;
+    uint32_t* s_pref = sh.pref;
+    uint32_t* s_w = sh.w;
     for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
         s_b[k] = 0;
         s_c[k] = 0;
     }
-    const uint32_t s0 = w.seg_off[blk], s1 = w.seg_off[blk + 1];
+    const uint32_t s0 = w.seg_off[gblk], s1 = w.seg_off[gblk + 1];
     for (uint32_t sb = s0; sb < s1; sb += kSegBatch) {
         const uint32_t nseg = min((uint32_t)kSegBatch, s1 - sb);
         uint32_t cnt = 0;
@@ -985,6 +1009,13 @@ __global__ void __launch_bounds__(kStage2Block) k_stage2(PartWs w, unsigned long
     }
 }
 
+__global__ void __launch_bounds__(kStage2Block) k_stage2(PartWs w, unsigned long long* count,
+                                                        unsigned long long* hbytes, uint32_t n_bins,
+                                                        int accumulate) {
+    __shared__ Stage2Shared sh;
+    stage2_block(w, sh, blockIdx.x, blockIdx.x, count, hbytes, n_bins, accumulate);
+}
+
 __global__ void k_zero(unsigned long long* __restrict__ p, uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -999,6 +1030,156 @@ __global__ void k_zero(unsigned long long* __restrict__ p, uint64_t n) {
 __global__ void k_zero32(uint32_t* __restrict__ p, uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent streams in one persistent launch.
+//
+// The paper's coordinated batch processing feeds uneven chunks through a work
+// queue so that every worker stays busy (sections "Coordinated Batch
+// Processing", "Work Queue", "TASK DECOMPOSITION").  Here the queue is a
+// device counter over (stream, chunk range) items that the persistent
+// workgroups pull until it is exhausted; a workgroup restages the table in
+// LDS only when the stream changes.  Partitioned streams share one workspace
+// (chunk and block index spaces concatenated), so one scan, one fill, one
+// stage-2 launch and one far pass serve all of them.  Streams with few bins
+// keep their whole histogram in LDS for the item and merge it with atomics.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+template <uint32_t KIND>
+__global__ void __launch_bounds__(kStage1Block) k_batch_stage1(BatchArgs a, PartWs w) {
+    extern __shared__ uint32_t lds[];
+    __shared__ Stage1Shared sh;
+    __shared__ uint32_t s_item;
+    const uint32_t tid = threadIdx.x;
+    uint32_t staged = 0xFFFFFFFFu;
+    LdsView v{};
+    uint32_t used = 0;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const uint32_t it = uniform_u32(s_item);
+        __syncthreads();
+        if (it >= a.n_items) break;
+        const uint4 item = a.items[it];
+        const uint32_t si = uniform_u32(item.x);
+        const BatchStreamDev& bs = a.streams[si];
+        const PassParams& p = bs.p;
+        if (si != staged) {
+            v = stage_lds<KIND>(p.t, lds, &used);  // ends with a barrier
+            staged = si;
+        }
+        Dropped d{};
+        if (bs.priv) {
+            PrivHist h;
+            const uint32_t base = (used + 1) & ~1u;
+            h.b = reinterpret_cast<unsigned long long*>(lds + base);
+            h.c = lds + base + 2 * 4 * p.n_bins;
+            for (uint32_t k = tid; k < 4 * p.n_bins; k += blockDim.x) {
+                h.b[k] = 0;
+                h.c[k] = 0;
+            }
+            __syncthreads();
+            const bool vec = w.vec != 0;
+            for (uint64_t c = item.y; c < item.z; ++c) {
+                const uint64_t g4 = c * (kChunk / 4) + tid;  // group of 4 sessions
+                if (vec && g4 * 4 + 4 <= p.n) {
+                    four_sessions<KIND, H_PRIVATE>(p, v, h, g4 * 4, d);
+                } else {
+                    for (uint64_t i = g4 * 4; i < p.n && i < g4 * 4 + 4; ++i)
+                        one_session<KIND, H_PRIVATE>(p, v, h, i, d);
+                }
+            }
+            __syncthreads();
+            for (uint32_t k = tid; k < 4 * p.n_bins; k += blockDim.x) {
+                if (h.c[k]) {
+                    __hip_atomic_fetch_add(p.count + k, (unsigned long long)h.c[k], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(p.hbytes + k, h.b[k], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            __syncthreads();
+        } else {
+            const bool vec = w.vec != 0;
+            auto full = [&](uint64_t c) { return vec && (c + 1) * kChunk <= p.n; };
+            Raw4 cur{}, nxt{};
+            uint64_t c = item.y;
+            if (c < item.z && full(c)) load4<KIND>(p, c * kChunk + (uint64_t)tid * 4, cur);
+            for (; c < item.z; ++c) {
+                if (c + 1 < item.z && full(c + 1)) load4<KIND>(p, (c + 1) * kChunk + (uint64_t)tid * 4, nxt);
+                stage1_chunk<KIND>(p, w, v, sh, c, bs.chunk0 + c, bs.block0, cur, full(c), d);
+                cur = nxt;
+            }
+        }
+        d.flush(p.dropped);
+    }
+}
+
+__global__ void __launch_bounds__(kStage2Block) k_batch_stage2(BatchArgs a, PartWs w) {
+    __shared__ Stage2Shared sh;
+    const uint32_t gb = blockIdx.x;
+    // stream owning the block: last s with block_base[s] <= gb
+    uint32_t lo = 0, n = a.n_streams;
+    while (n > 1) {
+        const uint32_t half = n >> 1;
+        lo = a.block_base[lo + half] <= gb ? lo + half : lo;
+        n -= half;
+    }
+    // skip streams without blocks (equal bases)
+    while (lo + 1 < a.n_streams && a.block_base[lo + 1] <= gb) ++lo;
+    const BatchStreamDev& bs = a.streams[lo];
+    stage2_block(w, sh, gb, gb - bs.block0, bs.p.count, bs.p.hbytes, bs.p.n_bins, 0);
+}
+
+template <uint32_t KIND>
+__global__ void __launch_bounds__(kMaxBlock) k_batch_far(BatchArgs a, PartWs w) {
+    extern __shared__ uint32_t lds[];
+    uint32_t staged = 0xFFFFFFFFu;
+    LdsView v{};
+    uint32_t used = 0;
+    const PrivHist h{nullptr, nullptr};
+    const uint32_t nfar = *w.farcount;
+    for (uint32_t q = blockIdx.x; q < nfar; q += gridDim.x) {
+        const uint64_t g = w.farlist[q];
+        uint32_t lo = 0, n = a.n_streams;
+        while (n > 1) {
+            const uint32_t half = n >> 1;
+            lo = a.chunk_base[lo + half] <= g ? lo + half : lo;
+            n -= half;
+        }
+        while (lo + 1 < a.n_streams && a.chunk_base[lo + 1] <= g) ++lo;
+        const uint32_t si = uniform_u32(lo);
+        const BatchStreamDev& bs = a.streams[si];
+        if (bs.priv || bs.p.t.kind != KIND) continue;  // another kind group's chunk
+        PassParams p = bs.p;
+        p.label_out = nullptr;
+        p.src_inst = nullptr;
+        p.dst_inst = nullptr;
+        p.dropped = nullptr;
+        if (si != staged) {
+            __syncthreads();
+            v = stage_lds<KIND>(p.t, lds, &used);
+            staged = si;
+        }
+        const uint64_t c = g - bs.chunk0;
+        Dropped d{};
+        for (uint32_t s = threadIdx.x; s < kChunk; s += blockDim.x) {
+            const uint64_t i = c * kChunk + s;
+            if (i < p.n && ((w.farbits[g * (kChunk / 32) + s / 32] >> (s & 31)) & 1u))
+                one_session<KIND, H_ATOMIC>(p, v, h, i, d);
+        }
+    }
+}
+
+__global__ void k_zero_jobs(const ZeroJob* __restrict__ jobs, uint32_t n_jobs) {
+    for (uint32_t j = blockIdx.x; j < n_jobs; j += gridDim.x) {
+        const ZeroJob z = jobs[j];
+        for (uint64_t k = threadIdx.x; k < z.n; k += blockDim.x) z.p[k] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,7 +1265,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 static bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 
 // Can the 4-session vector loads/stores be used for these pointers?
-static bool vector_ok(const PassParams& p, uint32_t kind, bool hist) {
+bool vector_ok(const PassParams& p, uint32_t kind, bool hist) {
     if (p.pos_out) return aligned16(p.src) && aligned16(p.pos_out);
     bool vec = true;
     if (kind == KK_LABEL_IN) vec = aligned4(p.label_in);
@@ -1176,6 +1357,23 @@ PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins) {
     return w;
 }
 
+// Segment index: exclusive scan of the per-block directory counts, then the
+// fill that groups directory entries by block.
+sinet_status launch_scan_fill(const PartWs& w, hipStream_t s) {
+    const uint32_t nb = w.n_blocks;
+    const uint32_t ntiles = (nb + 1 + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(1024), 0, s, w.seg_count, nb, w.scan_tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, w.scan_tiles, ntiles);
+    hipLaunchKernelGGL(k_scan_final, dim3(ntiles), dim3(1024), 0, s, w.seg_count, nb, w.scan_tiles,
+                       w.seg_off);
+    uint64_t fb = (w.n_chunks * kWin + 255) / 256;
+    const uint64_t cap = (uint64_t)device_cu_count() * 16;
+    if (fb > cap) fb = cap;
+    if (fb < 1) fb = 1;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)fb), dim3(256), 0, s, w);
+    return check_hip(hipGetLastError(), "segment index launch");
+}
+
 // Histogram of one stream by the partitioned path (workspace given).
 sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& w, int accumulate,
                              hipStream_t s) {
@@ -1196,16 +1394,8 @@ sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& 
     st = check_hip(hipGetLastError(), "stage-1 launch");
     if (st != SINET_OK) return st;
     const uint32_t nb = w.n_blocks;
-    const uint32_t ntiles = (nb + 1 + 1023) / 1024;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(1024), 0, s, w.seg_count, nb, w.scan_tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, w.scan_tiles, ntiles);
-    hipLaunchKernelGGL(k_scan_final, dim3(ntiles), dim3(1024), 0, s, w.seg_count, nb, w.scan_tiles,
-                       w.seg_off);
-    uint64_t fb = (w.n_chunks * kWin + 255) / 256;
-    const uint64_t cap = (uint64_t)device_cu_count() * 16;
-    if (fb > cap) fb = cap;
-    if (fb < 1) fb = 1;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)fb), dim3(256), 0, s, wv);
+    st = launch_scan_fill(wv, s);
+    if (st != SINET_OK) return st;
     hipLaunchKernelGGL(k_stage2, dim3(nb), dim3(kStage2Block), 0, s, wv, p.count, p.hbytes,
                        p.n_bins, accumulate);
     st = check_hip(hipGetLastError(), "stage-2 launch");
@@ -1218,6 +1408,72 @@ sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& 
     q.dst_inst = nullptr;
     q.dropped = nullptr;
     return launch_k_pass(q, kind, H_ATOMIC, false, far, 0, s);
+}
+
+// ---- batch launches -----------------------------------------------------------
+using BatchFn = void (*)(BatchArgs, PartWs);
+
+static BatchFn pick_batch_stage1(uint32_t kind) {
+    switch (kind) {
+        case KK_SCAN: return k_batch_stage1<KK_SCAN>;
+        case KK_BSEARCH: return k_batch_stage1<KK_BSEARCH>;
+        case KK_TRIE: return k_batch_stage1<KK_TRIE>;
+        case KK_PLA: return k_batch_stage1<KK_PLA>;
+        case KK_MLP: return k_batch_stage1<KK_MLP>;
+        case KK_INOUT: return k_batch_stage1<KK_INOUT>;
+        default: return nullptr;
+    }
+}
+
+static BatchFn pick_batch_far(uint32_t kind) {
+    switch (kind) {
+        case KK_SCAN: return k_batch_far<KK_SCAN>;
+        case KK_BSEARCH: return k_batch_far<KK_BSEARCH>;
+        case KK_TRIE: return k_batch_far<KK_TRIE>;
+        case KK_PLA: return k_batch_far<KK_PLA>;
+        case KK_MLP: return k_batch_far<KK_MLP>;
+        case KK_INOUT: return k_batch_far<KK_INOUT>;
+        default: return nullptr;
+    }
+}
+
+uint32_t batch_stage1_blocks_per_cu(uint32_t kind, size_t lds) {
+    BatchFn fn = pick_batch_stage1(kind);
+    return fn ? (uint32_t)blocks_per_cu((const void*)fn, kStage1Block, lds) : 1u;
+}
+
+sinet_status launch_batch_stage1(uint32_t kind, const BatchArgs& a, const PartWs& w, size_t lds,
+                                 uint32_t grid, hipStream_t s) {
+    BatchFn fn = pick_batch_stage1(kind);
+    if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no batch kernel for this lookup kind");
+    if (lds > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "batch needs more LDS than a CU has");
+    if (grid == 0) grid = device_cu_count() * blocks_per_cu((const void*)fn, kStage1Block, lds);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kStage1Block), lds, s, a, w);
+    return check_hip(hipGetLastError(), "batch stage-1 launch");
+}
+
+sinet_status launch_batch_stage2(const BatchArgs& a, const PartWs& w, uint32_t n_blocks,
+                                 hipStream_t s) {
+    if (n_blocks == 0) return SINET_OK;
+    hipLaunchKernelGGL(k_batch_stage2, dim3(n_blocks), dim3(kStage2Block), 0, s, a, w);
+    return check_hip(hipGetLastError(), "batch stage-2 launch");
+}
+
+sinet_status launch_batch_far(uint32_t kind, const BatchArgs& a, const PartWs& w, size_t lds,
+                              hipStream_t s) {
+    BatchFn fn = pick_batch_far(kind);
+    if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no batch kernel for this lookup kind");
+    const int block = lds > 40 * 1024 ? 1024 : 256;
+    const uint32_t grid = device_cu_count() * blocks_per_cu((const void*)fn, block, lds);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a, w);
+    return check_hip(hipGetLastError(), "batch far launch");
+}
+
+sinet_status launch_zero_jobs(const ZeroJob* jobs, uint32_t n_jobs, hipStream_t s) {
+    if (n_jobs == 0) return SINET_OK;
+    uint32_t grid = n_jobs < 4096 ? n_jobs : 4096;
+    hipLaunchKernelGGL(k_zero_jobs, dim3(grid), dim3(256), 0, s, jobs, n_jobs);
+    return check_hip(hipGetLastError(), "zero launch");
 }
 
 // ---- per-device pool for the stream-ordered workspace ------------------------

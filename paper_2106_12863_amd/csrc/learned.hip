@@ -305,15 +305,21 @@ k_mlp_partial(const float* __restrict__ w, const float* __restrict__ x,
 }
 
 // Sum the block partials (float64, fixed order), scale, and optionally apply
-// one Adam step (Kingma and Ba, 2015) to w.
-__global__ void k_mlp_finish(const float* __restrict__ partial, int nblocks, double inv_n,
-                             float* __restrict__ w, float* __restrict__ grad_out,
-                             float* __restrict__ loss_out, float* __restrict__ m1,
-                             float* __restrict__ m2, int step, float lr) {
-    const int k = threadIdx.x;
-    if (k >= kAcc) return;
+// one Adam step (Kingma and Ba, 2015) to w.  kFinishLanes lanes share one
+// accumulator: each sums a strided slice of the blocks, then a fixed shuffle
+// tree combines the slices.
+constexpr int kFinishLanes = 16;
+
+__global__ void __launch_bounds__(kAcc * kFinishLanes)
+k_mlp_finish(const float* __restrict__ partial, int nblocks, double inv_n,
+             float* __restrict__ w, float* __restrict__ grad_out, float* __restrict__ loss_out,
+             float* __restrict__ m1, float* __restrict__ m2, int step, float lr) {
+    const int k = threadIdx.x / kFinishLanes;
+    const int l = threadIdx.x % kFinishLanes;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += (double)partial[(uint64_t)b * kAcc + k];
+    for (int b = l; b < nblocks; b += kFinishLanes) s += (double)partial[(uint64_t)b * kAcc + k];
+    for (int o = kFinishLanes / 2; o > 0; o >>= 1) s += __shfl_down(s, o, kFinishLanes);
+    if (l != 0) return;
     if (k == kP) {
         if (loss_out) loss_out[0] = (float)(s * inv_n);
         return;
@@ -355,7 +361,8 @@ sinet_status mlp_loss_grad(const float* params, const float* x, const float* y, 
     hipLaunchKernelGGL(k_mlp_partial, dim3(nb), dim3(kGradBlock), 0, s, params, x, y, n, partial);
     e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_mlp_finish, dim3(1), dim3(64), 0, s, partial, nb, 1.0 / (double)n,
+        hipLaunchKernelGGL(k_mlp_finish, dim3(1), dim3(kAcc * kFinishLanes), 0, s, partial, nb,
+                           1.0 / (double)n,
                            (float*)nullptr, grad, loss, (float*)nullptr, (float*)nullptr, 0, 0.f);
         e = hipGetLastError();
     }
@@ -415,7 +422,8 @@ sinet_status train_mlp(sinet_table* t, const sinet_train_params* prm, hipStream_
         // the last launch only evaluates the final loss (no step)
         const bool last = it == steps + 1;
         float* lo = it == 1 ? lossd : (last ? lossd + 1 : nullptr);
-        hipLaunchKernelGGL(k_mlp_finish, dim3(1), dim3(64), 0, s, partial, nb, 1.0 / (double)m, w,
+        hipLaunchKernelGGL(k_mlp_finish, dim3(1), dim3(kAcc * kFinishLanes), 0, s, partial, nb,
+                           1.0 / (double)m, w,
                            (float*)nullptr, lo, state, state + kP, last ? 0 : (int)it, lr);
         e = hipGetLastError();
     }

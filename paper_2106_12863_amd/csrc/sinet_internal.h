@@ -74,6 +74,7 @@ constexpr int kChunk = 4096;        // sessions per stage-1 chunk
 constexpr int kBlockBins = 1024;    // bins per stage-2 block (all four labels)
 constexpr int kWin = 64;            // blocks one chunk may touch without the far path
 constexpr int kBigSlots = 128;      // 64-bit byte counts a chunk can hold out of line
+constexpr int kStage1Block = kChunk / 4;  // stage-1 lanes: 4 sessions each
 
 // Device workspace of the partitioned histogram (carved from one allocation).
 struct PartWs {
@@ -122,6 +123,31 @@ struct PassParams {
     uint64_t magic;             // ceil(2^64 / width) for width >= 2
 };
 
+// One stream of a batch as the batch kernels see it.
+struct BatchStreamDev {
+    PassParams p;               // label view of its table, columns, outputs, window
+    uint64_t chunk0;            // first workspace chunk (partitioned streams)
+    uint32_t block0;            // first workspace block (partitioned streams)
+    uint32_t priv;              // 1: histogram privatised in LDS, merged by atomics
+};
+
+struct BatchArgs {
+    const BatchStreamDev* streams;
+    const uint4* items;         // (stream, first chunk, end chunk, -) of one kind group
+    uint32_t n_items;
+    uint32_t n_streams;
+    uint32_t* counter;          // work-queue head of the group
+    const uint64_t* chunk_base; // [n_streams + 1] first workspace chunk of each stream
+    const uint32_t* block_base; // [n_streams + 1] first workspace block of each stream
+    uint32_t priv_bins;         // largest private histogram (bins) of the group
+    uint32_t pad;
+};
+
+struct ZeroJob {
+    unsigned long long* p;
+    uint64_t n;                 // 64-bit words
+};
+
 }  // namespace sinet
 
 struct sinet_table {
@@ -144,7 +170,13 @@ namespace sinet {
 sinet_status fail(sinet_status s, const std::string& msg);
 sinet_status check_hip(hipError_t e, const char* what);
 
+// api.cpp
+sinet_status check_usable(const sinet_table* t);
+sinet_status check_window(const sinet_window* w);
+DevTable label_view(const sinet_table* t, bool label_only);
+
 // kernels.hip
+bool vector_ok(const PassParams& p, uint32_t kind, bool hist);
 enum PassMode : uint32_t {
     PASS_LABEL = 1u,      // compute labels by lookup
     PASS_STORE = 2u,      // store labels
@@ -166,6 +198,17 @@ sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s);
 sinet_status ws_free(void* ptr, hipStream_t s);
 uint32_t device_cu_count();
 uint64_t div_magic(uint32_t width);
+
+// batch kernels (kernels.hip)
+sinet_status launch_batch_stage1(uint32_t kind, const BatchArgs& a, const PartWs& w, size_t lds,
+                                 uint32_t grid, hipStream_t s);
+sinet_status launch_batch_stage2(const BatchArgs& a, const PartWs& w, uint32_t n_blocks,
+                                 hipStream_t s);
+sinet_status launch_batch_far(uint32_t kind, const BatchArgs& a, const PartWs& w, size_t lds,
+                              hipStream_t s);
+sinet_status launch_zero_jobs(const ZeroJob* jobs, uint32_t n_jobs, hipStream_t s);
+sinet_status launch_scan_fill(const PartWs& w, hipStream_t s);
+uint32_t batch_stage1_blocks_per_cu(uint32_t kind, size_t lds);
 
 // learned.hip
 sinet_status train_pla(sinet_table* t, uint32_t segments, uint32_t target_err, uint32_t max_segments,

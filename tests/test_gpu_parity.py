@@ -424,3 +424,83 @@ def test_learned_forced_fallback_stays_exact(sinet, torch):
             torch.cuda.synchronize()
             assert np.array_equal(sinet.to_host_u32(pos2).astype(np.int64), learned.positions(B, q))
             assert tab2.info().fallbacks == 0
+
+
+# ------------------------------------------------------------------ batching
+def _batch_setup(sinet, torch, n_streams=10, total=2_000_000, inout=True):
+    import sinetgen.gpu as gg
+    streams = sinetgen.batch_streams(seed=33, n_streams=n_streams, total=total, hist_cap=3 << 30)
+    # two coarse streams whose histograms fit in LDS (the private path)
+    # (the tail beyond their last bin is dropped)
+    streams[0].window = sinetgen.Window(streams[0].t_origin, 1000, 500)
+    streams[1].window = sinetgen.Window(streams[1].t_origin + 123, 997, 1000)
+    built = []
+    for k, wl in enumerate(streams):
+        cols = gg.alloc_and_fill(wl)
+        # stream 2 uses the table's own search (a second kernel kind in the batch)
+        tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch", inout_index=inout and k != 2)
+        lab = torch.empty(wl.n, dtype=torch.uint8, device="cuda")
+        out = sinet.new_hist(wl.window.n_bins)
+        built.append((wl, cols, tab, lab, out))
+    torch.cuda.synchronize()
+    return built
+
+
+def _bstreams(sinet, built):
+    return [sinet.BatchStream(tab, c["ts"], c["src"], c["dst"], c["bytes"], wl.window.t0,
+                              wl.window.width, wl.window.n_bins, label=lab, out=out)
+            for wl, c, tab, lab, out in built]
+
+
+def test_batch_equals_per_stream_and_oracle(sinet, torch):
+    built = _batch_setup(sinet, torch)
+    _say("batch", [wl.n for wl, *_ in built])
+    plan = sinet.BatchPlan(_bstreams(sinet, built))
+    ref = []
+    for wl, c, tab, lab, out in built:
+        l2, o2 = sinet.pipeline(tab, c["ts"], c["src"], c["dst"], c["bytes"], wl.window.t0,
+                                wl.window.width, wl.window.n_bins)
+        ref.append((l2, o2))
+    for rep in range(3):   # graph replays, with eager work in between
+        for _, _, _, lab, out in built:
+            lab.fill_(7)
+            for t in out:
+                t.fill_(-1)
+        plan.run()
+        torch.cuda.synchronize()
+        for (wl, c, tab, lab, out), (l2, o2) in zip(built, ref):
+            assert torch.equal(lab, l2), (rep, wl.name)
+            for x, y in zip(out, o2):
+                assert torch.equal(x, y), (rep, wl.name)
+        _ = torch.randn(1000, device="cuda").sum()
+    # oracle on three streams (host regeneration)
+    for wl, c, tab, lab, out in built[:3]:
+        s = sinetgen.sessions(wl)
+        w = wl.window
+        elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"], s["bytes"],
+                                           w.t0, w.width, w.n_bins)
+        assert np.array_equal(lab.cpu().numpy(), elab), wl.name
+        _cmp_hist(sinet, out, (ec, eb, ed))
+
+
+def test_autotune_candidates_identical(sinet, torch, tmp_path):
+    built = _batch_setup(sinet, torch, n_streams=6, total=600_000)
+    bs = _bstreams(sinet, built)
+    cache = str(tmp_path / "tune.json")
+    t = sinet.autotune(bs, cache_path=cache)
+    assert t.chunk >= 4096 and t.block == 1024
+    t2 = sinet.autotune(bs, cache_path=cache)   # from the cache
+    assert (t2.chunk, t2.grid) == (t.chunk, t.grid)
+    outs = []
+    for chunk, grid in ((4096, 0), (65536, 0), (16384, 64), (t.chunk, t.grid)):
+        tune = sinet.Tune(1024, chunk, grid, 0)
+        plan = sinet.BatchPlan(bs, tune=tune)
+        plan.run()
+        torch.cuda.synchronize()
+        outs.append([(lab.clone(), [o.clone() for o in out]) for _, _, _, lab, out in built])
+        plan.close()
+    for o in outs[1:]:
+        for (l1, h1), (l2, h2) in zip(outs[0], o):
+            assert torch.equal(l1, l2)
+            for x, y in zip(h1, h2):
+                assert torch.equal(x, y)
