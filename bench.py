@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--day-streams", type=int, default=24, help="streams of the batched day")
+    ap.add_argument("--copy-gb", type=float, default=0.0,
+                    help="only run a plain device copy of this many GB (counter calibration)")
     return ap.parse_args()
 
 
@@ -244,6 +246,17 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
+    if args.copy_gb:
+        # a plain copy of known size: the reference that scales the HBM
+        # traffic counters (FETCH_SIZE / WRITE_SIZE) of the other kernels
+        n = int(args.copy_gb * 1e9) // 16
+        x = torch.ones(n, 2, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        ms, _, _ = time_calls(torch, lambda: y.copy_(x), max(1, args.steps), 1)
+        print(json.dumps({"copy_bytes_each_way": 16 * n, "ms": ms,
+                          "gbs_read_plus_write": 32 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
     import paper_2106_12863_amd as sinet
     import sinetgen
     import sinetgen.gpu as gg

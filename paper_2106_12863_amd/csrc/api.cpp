@@ -188,8 +188,8 @@ static uint32_t lds_bytes_for(const DevTable& t, uint32_t kind) {
         case SINET_LOOKUP_SCAN: return 12u * t.n_prefix;
         case SINET_LOOKUP_BSEARCH: words = t.n_top; break;
         case SINET_LOOKUP_TRIE: break;
-        case SINET_LOOKUP_LEARNED_PLA: words = 3 * t.segments + radix_words(t.radix_bits); break;
-        case SINET_LOOKUP_LEARNED_MLP: words = SINET_MLP_PARAMS; break;
+        case SINET_LOOKUP_LEARNED_PLA: words = t.n_top + 3 * t.segments + radix_words(t.radix_bits); break;
+        case SINET_LOOKUP_LEARNED_MLP: words = t.n_top + SINET_MLP_PARAMS; break;
         default: break;
     }
     return 4u * (words + t.lds_member_words + (t.filter_lds ? kFilterWords : 0u));
@@ -197,7 +197,8 @@ static uint32_t lds_bytes_for(const DevTable& t, uint32_t kind) {
 
 // LDS words a PLA of S segments needs next to the filter and member bits.
 static uint32_t pla_lds_words(const DevTable& t, uint32_t S) {
-    return 3 * S + radix_words(t.radix_bits) + t.lds_member_words + (t.filter_lds ? kFilterWords : 0u);
+    return t.n_top + 3 * S + radix_words(t.radix_bits) + t.lds_member_words +
+           (t.filter_lds ? kFilterWords : 0u);
 }
 
 // 2-bit state of every /16 block: 0 no prefix covers any of it, 1 one interval
@@ -324,7 +325,10 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     const uint32_t fw = filter_lds ? kFilterWords : 0u;
     const uint32_t member_lds =
         (mw <= kLdsMemberMaxWords && fw + mw + 1024 + kLdsReserveWords <= lds_words) ? mw : 0;
-    const uint32_t top_cap = std::min<uint32_t>(kLdsTopMax, lds_words - fw - member_lds - kLdsReserveWords);
+    // learned kinds keep fewer sampled boundaries, leaving LDS for the model
+    const bool learned_kind = kind == SINET_LOOKUP_LEARNED_PLA || kind == SINET_LOOKUP_LEARNED_MLP;
+    const uint32_t top_cap = std::min<uint32_t>(learned_kind ? kLdsTopMax / 2 : kLdsTopMax,
+                                                lds_words - fw - member_lds - kLdsReserveWords);
     uint32_t top_log2 = 0;
     while (((uint64_t)m + (1ull << top_log2) - 1) >> top_log2 > top_cap) ++top_log2;
     const uint32_t n_top = (uint32_t)(((uint64_t)m + (1ull << top_log2) - 1) >> top_log2);

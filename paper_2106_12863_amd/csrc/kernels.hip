@@ -51,9 +51,9 @@ enum KernelKind : uint32_t {
 
 constexpr int kXcds = 8;
 constexpr int kMaxBlock = 1024;
-constexpr int kStage2Block = 256;
+constexpr int kStage2Block = 512;
 constexpr int kSegBatch = kStage2Block;    // segments staged per stage-2 round
-constexpr int kRecUnroll = 8;              // independent record loads per stage-2 lane
+constexpr int kRecUnroll = 4;              // independent record loads per stage-2 lane
 constexpr uint32_t kSmallMax = 1u << 19;  // byte counts stored inline in a record
 constexpr uint64_t kMaxPiece = 1ull << 31;  // sessions per partitioned pass (32-bit slots)
 
@@ -112,47 +112,71 @@ __device__ __forceinline__ uint32_t radix_entry(const uint32_t* radix, uint32_t 
     return (radix[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
 }
 
-// Learned forms: the model's rounded prediction p is within max_err of the
-// true interval for every boundary key; search a window of W = 2 e + 1
-// boundaries around p (shifted inside [0, m)) and confirm the bracket
-// B[j] <= a < B[j+1], else fall back to the full search.
+// Leaf phase shared by the binary search and the learned kinds: j[q] holds a
+// leaf-block index (an index into the sampled boundaries); the leaf's
+// 2^top_log2 boundaries (one or two cache lines, padded with 0xFFFFFFFF) are
+// searched in global memory.
 template <int N>
-__device__ __forceinline__ void bounded_search_n(const DevTable& t, const uint32_t* a, const int* p,
-                                                 uint32_t* j, uint32_t need) {
-    const uint32_t W = min(2 * t.max_err + 1, t.m);
-    uint32_t lo[N];
-    bool ok[N];
+__device__ __forceinline__ void leaf_search(const DevTable& t, const uint32_t* a, uint32_t* j,
+                                            uint32_t need) {
+    if (t.top_log2 == 0) return;
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-        int l = p[q] - (int)t.max_err;
-        l = l < 0 ? 0 : l;
-        l = (uint32_t)l + W > t.m ? (int)(t.m - W) : l;
-        lo[q] = (uint32_t)l;
-    }
-#pragma unroll
-    for (int q = 0; q < N; ++q) ok[q] = (need >> q) & 1u ? t.B[lo[q]] <= a[q] : true;
-    uint32_t first[N];
-#pragma unroll
-    for (int q = 0; q < N; ++q) first[q] = lo[q];
-    uint32_t n = W;
+    for (int q = 0; q < N; ++q) j[q] <<= t.top_log2;
+    uint32_t n = 1u << t.top_log2;
     while (n > 1) {
         const uint32_t half = n >> 1;
 #pragma unroll
         for (int q = 0; q < N; ++q)
-            if ((need >> q) & 1u) lo[q] = (t.B[lo[q] + half] <= a[q]) ? lo[q] + half : lo[q];
+            if ((need >> q) & 1u) j[q] = (t.B[j[q] + half] <= a[q]) ? j[q] + half : j[q];
+        n -= half;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) j[q] = min(j[q], t.m - 1);
+}
+
+// Learned forms: the model's rounded prediction p is within max_err = e of
+// the true interval j for every boundary key.  The leaf blocks that
+// [p - e, p + e] can touch are searched in the LDS copy of the sampled
+// boundaries (a window of uniform length, shifted inside the array), the
+// bracket top[b] <= a < top[b + 1] is confirmed, and the leaf is searched as in
+// the plain binary search.  A failed bracket (a wrong model or bound) falls
+// back to the full search and is counted, so results stay exact.
+template <int N>
+__device__ __forceinline__ void learned_search_n(const DevTable& t, const LdsView& v,
+                                                 const uint32_t* a, const int* p, uint32_t* j,
+                                                 uint32_t need) {
+    const uint32_t L = t.top_log2;
+    const uint32_t nbl = min(((2 * t.max_err) >> L) + 2, t.n_top);
+    uint32_t b[N], first[N];
+    bool ok[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const int lo = max(p[q] - (int)t.max_err, 0);
+        uint32_t b0 = (uint32_t)lo >> L;
+        b0 = min(b0, t.n_top - nbl);
+        first[q] = b0;
+        b[q] = b0;
+        ok[q] = v.top[b0] <= a[q];
+    }
+    uint32_t n = nbl;
+    while (n > 1) {
+        const uint32_t half = n >> 1;
+#pragma unroll
+        for (int q = 0; q < N; ++q) b[q] = (v.top[b[q] + half] <= a[q]) ? b[q] + half : b[q];
         n -= half;
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         if (!((need >> q) & 1u)) continue;
-        const uint32_t last = first[q] + W - 1;
-        if (ok[q] && lo[q] == last && last + 1 < t.m && t.B[last + 1] <= a[q]) ok[q] = false;
-        j[q] = lo[q];
+        const uint32_t last = first[q] + nbl - 1;
+        if (ok[q] && b[q] == last && last + 1 < t.n_top && v.top[last + 1] <= a[q]) ok[q] = false;
         if (!ok[q]) {
             atomicAdd(t.fallbacks, 1ull);
-            j[q] = upper_last(t.B, t.m, a[q]);
+            b[q] = upper_last(v.top, t.n_top, a[q]);
         }
+        j[q] = b[q];
     }
+    leaf_search<N>(t, a, j, need);
 }
 
 // Interval index of each address (all kinds but SCAN).  Addresses whose bit
@@ -163,20 +187,7 @@ __device__ __forceinline__ void intervals(const DevTable& t, const LdsView& v, c
                                           uint32_t* j, uint32_t need = 0xFFFFFFFFu) {
     if constexpr (KIND == KK_BSEARCH) {
         upper_last_n<N>(v.top, t.n_top, a, j);
-        if (t.top_log2 == 0) return;
-        // the boundary array is padded with 0xFFFFFFFF to whole leaf blocks
-#pragma unroll
-        for (int q = 0; q < N; ++q) j[q] <<= t.top_log2;
-        uint32_t n = 1u << t.top_log2;
-        while (n > 1) {
-            const uint32_t half = n >> 1;
-#pragma unroll
-            for (int q = 0; q < N; ++q)
-                if ((need >> q) & 1u) j[q] = (t.B[j[q] + half] <= a[q]) ? j[q] + half : j[q];
-            n -= half;
-        }
-#pragma unroll
-        for (int q = 0; q < N; ++q) j[q] = min(j[q], t.m - 1);
+        leaf_search<N>(t, a, j, need);
     } else if constexpr (KIND == KK_TRIE) {
         uint32_t e[N];
 #pragma unroll
@@ -201,13 +212,13 @@ __device__ __forceinline__ void intervals(const DevTable& t, const LdsView& v, c
             const uint32_t s = s0 + upper_last(v.knot + s0, s1 - s0 + 1, a[q]);
             p[q] = clamp_pos(pla_eval(v.knot[s], v.c[s], v.g[s], a[q]), t.m);
         }
-        bounded_search_n<N>(t, a, p, j, need);
+        learned_search_n<N>(t, v, a, p, j, need);
     } else {  // KK_MLP
         int p[N];
 #pragma unroll
         for (int q = 0; q < N; ++q)
             p[q] = (need >> q) & 1u ? clamp_pos(mlp_predict(v.w, t.m_f, a[q]), t.m) : 0;
-        bounded_search_n<N>(t, a, p, j, need);
+        learned_search_n<N>(t, v, a, p, j, need);
     }
 }
 
@@ -515,7 +526,8 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) 
         v.len = copy(t.len, t.n_prefix);
     } else if constexpr (KIND != KK_LABEL_IN) {
         v.filter = t.filter_lds ? copy(t.filter, kFilterWords) : t.filter;
-        if constexpr (KIND == KK_BSEARCH) v.top = copy(t.top, t.n_top);
+        if constexpr (KIND == KK_BSEARCH || KIND == KK_PLA || KIND == KK_MLP)
+            v.top = copy(t.top, t.n_top);
         if constexpr (KIND == KK_PLA) {
             v.knot = copy(t.knot, t.segments);
             v.c = reinterpret_cast<const float*>(
@@ -583,6 +595,39 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
         const uint64_t cum = (uint64_t)xcd * per + min(xcd, rem);
         const uint64_t T0 = n_tiles * cum / W;
         const uint64_t T1 = n_tiles * (cum + nx) / W;
+        if constexpr (HM == H_NONE && VEC && KIND != KK_LABEL_IN) {
+            if (!p.pos_out) {
+                // labels / institutions only: the next tile's addresses are
+                // loaded before the current tile's lookups run
+                auto full = [&](uint64_t tl) { return (tl * tile + threadIdx.x) * 4 + 4 <= p.n; };
+                uint4 cs = make_uint4(0, 0, 0, 0), cd = cs, ns = cs, nd = cs;
+                uint64_t tl = T0 + lid;
+                if (tl < T1 && full(tl)) {
+                    const uint64_t i = (tl * tile + threadIdx.x) * 4;
+                    cs = *reinterpret_cast<const uint4*>(p.src + i);
+                    cd = *reinterpret_cast<const uint4*>(p.dst + i);
+                }
+                for (; tl < T1; tl += nx) {
+                    const uint64_t tn = tl + nx;
+                    if (tn < T1 && full(tn)) {
+                        const uint64_t i = (tn * tile + threadIdx.x) * 4;
+                        ns = *reinterpret_cast<const uint4*>(p.src + i);
+                        nd = *reinterpret_cast<const uint4*>(p.dst + i);
+                    }
+                    const uint64_t g = tl * tile + threadIdx.x;
+                    if (full(tl)) {
+                        uint32_t lab[4];
+                        labels4_from<KIND>(p, v, g * 4, cs, cd, 0u, lab);
+                    } else if (g * 4 < p.n) {
+                        for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
+                            one_session<KIND, HM>(p, v, h, i, d);
+                    }
+                    cs = ns;
+                    cd = nd;
+                }
+                return;
+            }
+        }
         for (uint64_t tl = T0 + lid; tl < T1; tl += nx) {
             const uint64_t g = tl * tile + threadIdx.x;
             if (g >= groups) continue;
@@ -922,49 +967,53 @@ __device__ __forceinline__ void stage2_block(const PartWs& w, Stage2Shared& sh, 
         s_c[k] = 0;
     }
     const uint32_t s0 = w.seg_off[gblk], s1 = w.seg_off[gblk + 1];
+    // Segments are taken kSegBatch at a time; each wave walks whole segments
+    // (contiguous records, so a wave's loads are coalesced) with kRecUnroll
+    // independent loads in flight per lane.
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    constexpr uint32_t kWaves = kStage2Block / 64;
     for (uint32_t sb = s0; sb < s1; sb += kSegBatch) {
         const uint32_t nseg = min((uint32_t)kSegBatch, s1 - sb);
-        uint32_t cnt = 0;
         if (threadIdx.x < nseg) {
             const uint2 sg = w.segs[sb + threadIdx.x];
             s_start[threadIdx.x] = sg.x;
-            cnt = sg.y;
+            s_pref[threadIdx.x] = sg.y;  // count
         }
-        const uint32_t inc = block_incl_scan(cnt, s_w);  // includes the barriers
-        if (threadIdx.x < nseg) s_pref[threadIdx.x] = inc - cnt;
-        if (threadIdx.x == kStage2Block - 1) s_pref[nseg] = inc;
         __syncthreads();
-        const uint32_t total = s_pref[nseg];
-        // kRecUnroll independent record loads in flight per lane
-        for (uint32_t r0 = 0; r0 < total; r0 += kStage2Block * kRecUnroll) {
-            uint32_t rec[kRecUnroll], slot[kRecUnroll];
-#pragma unroll
-            for (int u = 0; u < kRecUnroll; ++u) {
-                const uint32_t r = r0 + u * kStage2Block + threadIdx.x;
-                slot[u] = 0xFFFFFFFFu;
-                rec[u] = 0;
-                if (r < total) {
-                    // segment j holding flat record r: last j with s_pref[j] <= r
-                    uint32_t lo = 0, n = nseg;
-                    while (n > 1) {
-                        const uint32_t half = n >> 1;
-                        lo = s_pref[lo + half] <= r ? lo + half : lo;
-                        n -= half;
-                    }
-                    slot[u] = s_start[lo] + (r - s_pref[lo]);
-                    rec[u] = w.rec[slot[u]];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kRecUnroll; ++u) {
-                if (slot[u] == 0xFFFFFFFFu) continue;
-                const uint32_t key = rec[u] >> 20;  // label * kBlockBins + offset
+        for (uint32_t j = wave; j < nseg; j += kWaves) {
+            const uint32_t start = s_start[j], cnt = s_pref[j];
+            const uint64_t chunk = start / kChunk;
+            auto add = [&](uint32_t r) {
+                const uint32_t key = r >> 20;  // label * kBlockBins + offset
                 const unsigned long long v =
-                    (rec[u] >> 19) & 1u
-                        ? w.big[(uint64_t)(slot[u] / kChunk) * kBigSlots + (rec[u] & 0x7FFFFu)]
-                        : (unsigned long long)(rec[u] & 0x7FFFFu);
+                    (r >> 19) & 1u ? w.big[chunk * kBigSlots + (r & 0x7FFFFu)]
+                                   : (unsigned long long)(r & 0x7FFFFu);
                 atomicAdd(&s_c[key], 1u);
                 atomicAdd(&s_b[key], v);
+            };
+            // unaligned head and tail one record per lane, the 16-byte aligned
+            // body four records per load, kRecUnroll loads in flight per lane
+            const uint32_t a0 = min((start + 3u) & ~3u, start + cnt);
+            const uint32_t a1 = max(a0, (start + cnt) & ~3u);
+            if (lane < a0 - start) add(w.rec[(uint64_t)start + lane]);
+            if (lane < start + cnt - a1) add(w.rec[(uint64_t)a1 + lane]);
+            const uint4* body = reinterpret_cast<const uint4*>(w.rec + a0);
+            const uint32_t nv = (a1 - a0) / 4;
+            for (uint32_t v0 = 0; v0 < nv; v0 += 64 * kRecUnroll) {
+                uint4 r4[kRecUnroll];
+#pragma unroll
+                for (int u = 0; u < kRecUnroll; ++u) {
+                    const uint32_t vi = v0 + u * 64 + lane;
+                    r4[u] = vi < nv ? body[vi] : make_uint4(0xFFFFFFFFu, 0, 0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < kRecUnroll; ++u) {
+                    if (v0 + u * 64 + lane >= nv) continue;
+                    add(r4[u].x);
+                    add(r4[u].y);
+                    add(r4[u].z);
+                    add(r4[u].w);
+                }
             }
         }
         __syncthreads();
@@ -1550,11 +1599,31 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
         q.label_out = p.label_out ? p.label_out + lo : nullptr;
         q.src_inst = p.src_inst ? p.src_inst + lo : nullptr;
         q.dst_inst = p.dst_inst ? p.dst_inst + lo : nullptr;
+        // Lookups that walk global memory (trie, learned windows, large binary
+        // searches) run as their own barrier-free pass; stage 1 then reads the
+        // labels (1 byte per session) instead of stalling its barriers on them.
+        const bool split = kind == KK_TRIE || kind == KK_PLA || kind == KK_MLP ||
+                           (kind == KK_BSEARCH && p.t.top_log2 > 0);
+        const size_t wsb = part_ws_bytes(len, p.n_bins);
+        const size_t lab_bytes = split && !q.label_out ? ((len + 255) & ~(uint64_t)255) : 0;
         void* ws = nullptr;
-        sinet_status st = ws_alloc(&ws, part_ws_bytes(len, p.n_bins), s);
+        sinet_status st = ws_alloc(&ws, wsb + lab_bytes, s);
         if (st != SINET_OK) return st;
         const PartWs w = part_ws_carve(ws, len, p.n_bins);
-        st = run_partitioned(q, kind, w, acc, s);
+        uint32_t k2 = kind;
+        if (split) {
+            PassParams lq = q;
+            if (!lq.label_out) lq.label_out = (uint8_t*)ws + wsb;
+            lq.pos_out = nullptr;
+            FarList none{};
+            st = launch_k_pass(lq, kind, H_NONE, vector_ok(lq, kind, false), none, 0, s);
+            q.label_in = lq.label_out;
+            q.label_out = nullptr;
+            q.src_inst = nullptr;
+            q.dst_inst = nullptr;
+            k2 = KK_LABEL_IN;
+        }
+        if (st == SINET_OK) st = run_partitioned(q, k2, w, acc, s);
         sinet_status st2 = ws_free(ws, s);
         if (st != SINET_OK) return st;
         if (st2 != SINET_OK) return st2;

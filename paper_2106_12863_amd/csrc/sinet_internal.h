@@ -70,7 +70,7 @@ __host__ __device__ constexpr uint32_t radix_words(uint32_t bits) {
 }
 
 // Partitioned histogram geometry.
-constexpr int kChunk = 4096;        // sessions per stage-1 chunk
+constexpr int kChunk = 2048;        // sessions per stage-1 chunk
 constexpr int kBlockBins = 1024;    // bins per stage-2 block (all four labels)
 constexpr int kWin = 64;            // blocks one chunk may touch without the far path
 constexpr int kBigSlots = 128;      // 64-bit byte counts a chunk can hold out of line

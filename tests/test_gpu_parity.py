@@ -488,7 +488,7 @@ def test_autotune_candidates_identical(sinet, torch, tmp_path):
     bs = _bstreams(sinet, built)
     cache = str(tmp_path / "tune.json")
     t = sinet.autotune(bs, cache_path=cache)
-    assert t.chunk >= 4096 and t.block == 1024
+    assert t.chunk >= 2048 and t.block in (512, 1024)
     t2 = sinet.autotune(bs, cache_path=cache)   # from the cache
     assert (t2.chunk, t2.grid) == (t.chunk, t.grid)
     outs = []
