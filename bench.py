@@ -10,11 +10,14 @@ Inputs are synthetic (seeded generator writing straight into HBM) with the
 paper's day shape.
 
 Forms timed on the same resident day (the first is the headline value):
-  plain        bsearch table, labels from its in/out index (LDS)
-  bsearch      plain binary search over the interval boundaries (no index)
-  trie         16-8-8 multibit trie (no index)
-  pla          learned: error-bounded piecewise-linear model + bounded search
-  mlp          learned: 1-16-1 ReLU MLP + bounded search
+  plain        labels from the table's in/out index (LDS)
+  bsearch      plain binary search over the interval boundaries in global memory
+  bsearch_lds  binary search with the top levels (sampled boundaries) in LDS
+  trie         16-8-8 multibit trie
+  pla          learned: error-bounded piecewise-linear model, window search in the
+               LDS sampled boundaries, then the boundary leaf
+  mlp          learned: 1-16-1 ReLU MLP, same window search
+  (every form but plain runs its own search for every address)
   batched      the day cut into time-ordered streams, one graph launch
                (table with the learned PLA and the in/out index)
 
@@ -36,7 +39,9 @@ METRIC = "sessions/sec classify+histogram on 1 GPU, % HBM roofline; learned vs p
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SESSION = 21   # ts 4 + src 4 + dst 4 + bytes 8 read, label 1 written
 BYTES_PER_BIN = 64       # 4 labels x (count 8 + bytes 8) written once
-DEFAULT_FORMS = "plain,bsearch,trie,pla,mlp,batched"
+DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched"
+# HBM bytes per launch from the counter runs (see measured_traffic)
+COUNTER_TRAFFIC = {}
 
 
 def log(*a):
@@ -59,16 +64,19 @@ def parse():
     return ap.parse_args()
 
 
-def time_calls(torch, fn, steps, warmup):
+def time_calls(torch, fn, steps, warmup, sinet=None):
     """Average and minimum device ms per call from HIP events recorded on the
-    stream the library launches on (torch's current stream), plus host wall
-    ms per call over the timed loop."""
+    stream the library launches on (torch's current stream), host wall ms per
+    call over the timed loop, and (when sinet is given) the library's own
+    per-phase event timing summed over the timed calls."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
+    if sinet is not None:
+        sinet.timing_enable(True)
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(st)
@@ -76,8 +84,52 @@ def time_calls(torch, fn, steps, warmup):
         b.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    phases = None
+    if sinet is not None:
+        phases = sinet.timing_read()
+        sinet.timing_enable(False)
     dev = [a.elapsed_time(b) for a, b in evs]
-    return sum(dev) / len(dev), min(dev), wall * 1e3 / steps
+    return sum(dev) / len(dev), min(dev), wall * 1e3 / steps, phases
+
+
+def kernel_roofline(phases, n, n_bins, steps):
+    """Roofline of the dominant kernel of the step from the library's phase
+    events over the timed calls: the stage-1 kernel (read ts/src/dst/bytes,
+    20 B, and write the label, 1 B, per session) or the stage-2 kernel (write
+    every bin once, 64 B per bin), whichever takes longer."""
+    if phases is None or phases["stage1_launches"] == 0:
+        return None
+    launches = phases["stage1_launches"]
+    cand = []
+    # the fused stage 1 carries the whole per-session traffic; after a
+    # separate lookup pass it reads ts, bytes and the stored label (13 B)
+    fused = phases["lookup_ms"] == 0.0
+    cand.append(("k_stage1", phases["stage1_ms"] / launches,
+                 (BYTES_PER_SESSION if fused else 13) * n / launches))
+    if phases["stage2_ms"] > 0:
+        cand.append(("k_stage2", phases["stage2_ms"] / launches, BYTES_PER_BIN * n_bins / launches))
+    if not fused:
+        cand.append(("k_pass (lookup, labels stored)", phases["lookup_ms"] / launches, 9 * n / launches))
+    name, ms, alg = max(cand, key=lambda c: c[1])
+    achieved = alg / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(name)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
+            "alg_bytes_per_launch": alg, "launch_ms": ms, "launches": launches, "steps": steps}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the kernel from the FETCH_SIZE / WRITE_SIZE
+    counter runs of the default workload, scaled by the same counters of a
+    plain copy; null when the kernel source has changed since."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2106_12863_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    rec = COUNTER_TRAFFIC.get(kernel)
+    if rec is None or rec["kernels_sha"] != sha:
+        return None
+    return rec["bytes"]
 
 
 def cpu_baseline(wl, cols, sinet, sample: int):
@@ -127,7 +179,8 @@ def day_streams(sinet, wl, cols, tab, k, label, out):
 
 def bench_day(args, torch, sinet, sinetgen, gg):
     wl = sinetgen.config(args.config, n=args.n or None)
-    forms = (args.forms or (DEFAULT_FORMS if args.config in (4, 5) else "plain,bsearch,trie")).split(",")
+    forms = (args.forms or (DEFAULT_FORMS if args.config in (4, 5) else
+                            "plain,bsearch,bsearch_lds,trie")).split(",")
     log(f"config {args.config}: {wl.name} n={wl.n} prefixes={wl.n_prefix} forms={forms}")
     cols = gg.alloc_and_fill(wl)
     torch.cuda.synchronize()
@@ -144,13 +197,15 @@ def bench_day(args, torch, sinet, sinetgen, gg):
             plan = sinet.BatchPlan(streams, tune=tune)
             fn = plan.run
         else:
-            kind = "bsearch" if form == "plain" else form
-            tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=(form == "plain"))
+            kind = "bsearch" if form in ("plain", "bsearch_lds") else form
+            tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=(form == "plain"),
+                              global_bsearch=(form == "bsearch"))
             rep = tab.train() if kind in ("pla", "mlp") else None
             fn = (lambda t=tab: sinet.pipeline(t, cols["ts"], cols["src"], cols["dst"],
                                                cols["bytes"], w.t0, w.width, w.n_bins,
                                                label=label, out=out))
-        ms, ms_min, wall = time_calls(torch, fn, args.steps, args.warmup)
+        ms, ms_min, wall, phases = time_calls(torch, fn, args.steps, args.warmup,
+                                              None if form == "batched" else sinet)
         info = tab.info()
         results[form] = {"sessions_per_s": wl.n / (ms * 1e-3), "ms_per_step": ms, "ms_min": ms_min,
                          "wall_ms": wall, "kind": sinet.KIND_NAMES[info.kind],
@@ -158,6 +213,11 @@ def bench_day(args, torch, sinet, sinetgen, gg):
                          "m": int(info.m), "max_err": int(info.max_err),
                          "segments": int(info.segments), "fallbacks": int(info.fallbacks),
                          "train_ms": None if rep is None else round(rep.train_ms, 3)}
+        if phases is not None:
+            results[form]["phases_ms_per_step"] = {
+                k[:-3]: phases[k] / args.steps
+                for k in ("lookup_ms", "stage1_ms", "index_ms", "stage2_ms", "far_ms")}
+            results[form]["_phases"] = phases
         if form == "batched":
             results[form]["tune"] = {"block": tune.block, "chunk": tune.chunk, "grid": tune.grid}
             results[form]["streams"] = len(streams)
@@ -167,7 +227,7 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     head = forms[0]
     r = results[head]
     alg_bytes = BYTES_PER_SESSION * wl.n + BYTES_PER_BIN * w.n_bins
-    achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+    roof = kernel_roofline(r.get("_phases"), wl.n, w.n_bins, args.steps)
     line = {
         "metric": METRIC, "value": r["sessions_per_s"], "unit": "sessions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -176,12 +236,11 @@ def bench_day(args, torch, sinet, sinetgen, gg):
         "config": {"workload": wl.name, "n_sessions": wl.n, "n_prefix": wl.n_prefix,
                    "n_bins": w.n_bins, "bin_ms": w.width, "form": head,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "one sinet_pipeline step: k_stage1 (lookup + label + partition) "
-                               "+ segment index + k_stage2 (block reduce, one write per bin)",
-                     "alg_bytes_per_launch": alg_bytes, "launch_ms": r["ms_per_step"]},
-        "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("wall_ms",)}
+        "roofline": roof,
+        "step_roofline": {"alg_bytes": alg_bytes, "ms": r["ms_per_step"],
+                          "achieved": alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9,
+                          "frac": alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("wall_ms", "_phases")}
                   for k, v in results.items()},
     }
     for k, v in results.items():
@@ -218,8 +277,8 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
 
     n = sum(wl.n for wl in streams_wl)
     bins = sum(wl.window.n_bins for wl in streams_wl)
-    ms_b, min_b, _ = time_calls(torch, plan.run, args.steps, args.warmup)
-    ms_p, min_p, _ = time_calls(torch, per_stream, args.steps, args.warmup)
+    ms_b, min_b, _, _ = time_calls(torch, plan.run, args.steps, args.warmup)
+    ms_p, min_p, _, _ = time_calls(torch, per_stream, args.steps, args.warmup)
     alg_bytes = BYTES_PER_SESSION * n + BYTES_PER_BIN * bins
     achieved = alg_bytes / (ms_b * 1e-3) / 1e9
     return {
@@ -253,7 +312,7 @@ def main():
         x = torch.ones(n, 2, dtype=torch.int64, device="cuda")
         y = torch.empty_like(x)
         torch.cuda.synchronize()
-        ms, _, _ = time_calls(torch, lambda: y.copy_(x), max(1, args.steps), 1)
+        ms, _, _, _ = time_calls(torch, lambda: y.copy_(x), max(1, args.steps), 1)
         print(json.dumps({"copy_bytes_each_way": 16 * n, "ms": ms,
                           "gbs_read_plus_write": 32 * n / (ms * 1e-3) / 1e9}), flush=True)
         return

@@ -75,6 +75,10 @@ typedef enum {
 /* OR-ed into the kind argument of sinet_table_create: do not build the
  * in/out index, so label-only queries also run the kind's own search. */
 #define SINET_TABLE_NO_INOUT_INDEX 0x100u
+/* OR-ed into the kind argument: a BSEARCH table searches the boundaries in
+ * global memory from the first probe (no LDS copy of sampled boundaries),
+ * i.e. the plain binary search. */
+#define SINET_TABLE_GLOBAL_BSEARCH 0x200u
 
 #define SINET_NO_INST 0xFFFFFFFFu
 #define SINET_MAX_PREFIXES (1u << 22)
@@ -267,6 +271,33 @@ sinet_status sinet_batch_plan_create(const sinet_stream* streams, uint32_t n_str
 sinet_status sinet_batch_run(sinet_batch_plan* plan, hipStream_t stream);
 
 sinet_status sinet_batch_plan_destroy(sinet_batch_plan* plan);
+
+/* Device time of the phases of sinet_histogram / sinet_pipeline, summed over
+ * the calls made since timing was last enabled.  Each phase is bracketed by
+ * a pair of HIP events recorded on the call's own stream (none while the
+ * stream is being captured into a graph), so a phase's figure is the device
+ * time of its kernels on that stream. */
+typedef struct {
+    double lookup_ms;   /* separate lookup pass that stores labels before stage 1
+                           (trie, learned and sampled-boundary searches); 0 when fused */
+    double stage1_ms;   /* k_stage1: classify, bin, partition into records; for
+                           n_bins <= 2048 the single private-histogram pass instead */
+    double index_ms;    /* per-block segment scan and directory fill */
+    double stage2_ms;   /* k_stage2: block reduction, one write of every bin */
+    double far_ms;      /* far pass (out-of-partition sessions, global atomics) */
+    uint64_t calls;     /* timed sinet_histogram / sinet_pipeline calls */
+    uint64_t stage1_launches;  /* stage-1 (or private-pass) launches among them */
+} sinet_timing;
+
+/* on != 0: start timing every later sinet_histogram / sinet_pipeline call of
+ * this process (clears earlier figures); on == 0: stop.  Timing costs two
+ * event records per phase.  Not thread-safe against concurrent calls of
+ * sinet_timing_read. */
+sinet_status sinet_timing_enable(int on);
+
+/* Wait for the recorded events and return the sums since the last enable.
+ * Errors: INVALID_ARG (out NULL), HIP (event failure). */
+sinet_status sinet_timing_read(sinet_timing* out);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,7 @@ MLP_PARAMS = 49
 KINDS = {"auto": 0, "scan": 1, "bsearch": 2, "trie": 3, "pla": 4, "mlp": 5}
 KIND_NAMES = {v: k for k, v in KINDS.items()}
 NO_INOUT_INDEX = 0x100
+GLOBAL_BSEARCH = 0x200
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libsinet is not built ({LIB_PATH} missing): run __graft_entry__.build()")
@@ -70,6 +71,12 @@ class Stream(ctypes.Structure):
     _fields_ = [("cols", Columns), ("table", P), ("win", Window), ("label", P), ("hist", Hist)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("lookup_ms", ctypes.c_double), ("stage1_ms", ctypes.c_double),
+                ("index_ms", ctypes.c_double), ("stage2_ms", ctypes.c_double),
+                ("far_ms", ctypes.c_double), ("calls", U64), ("stage1_launches", U64)]
+
+
 def _sig(name, args, res=I32):
     f = getattr(_lib, name)
     f.argtypes = args
@@ -97,6 +104,8 @@ _sig("sinet_autotune", [P, U32, ctypes.c_char_p, P, ctypes.POINTER(Tune)])
 _sig("sinet_batch_plan_create", [P, U32, ctypes.POINTER(Tune), P, ctypes.POINTER(P)])
 _sig("sinet_batch_run", [P, P])
 _sig("sinet_batch_plan_destroy", [P])
+_sig("sinet_timing_enable", [I32])
+_sig("sinet_timing_read", [ctypes.POINTER(Timing)])
 
 
 class SinetError(RuntimeError):
@@ -137,7 +146,8 @@ def _dev_check(*ts):
 class Table:
     """Device-resident prefix table (library-owned)."""
 
-    def __init__(self, base, plen, inst=None, kind: str = "auto", inout_index: bool = True):
+    def __init__(self, base, plen, inst=None, kind: str = "auto", inout_index: bool = True,
+                 global_bsearch: bool = False):
         base = np.ascontiguousarray(base, dtype=np.uint32)
         plen = np.ascontiguousarray(plen, dtype=np.uint8)
         self._inst = None if inst is None else np.ascontiguousarray(inst, dtype=np.uint32)
@@ -145,7 +155,8 @@ class Table:
         rc = _lib.sinet_table_create(base.ctypes.data_as(P), plen.ctypes.data_as(P),
                                      None if self._inst is None else self._inst.ctypes.data_as(P),
                                      base.shape[0],
-                                     KINDS[kind] | (0 if inout_index else NO_INOUT_INDEX),
+                                     KINDS[kind] | (0 if inout_index else NO_INOUT_INDEX)
+                                     | (GLOBAL_BSEARCH if global_bsearch else 0),
                                      _stream(), ctypes.byref(out))
         _check(rc, "sinet_table_create")
         self.handle = out
@@ -371,6 +382,19 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def timing_enable(on: bool = True):
+    """Start (clearing earlier figures) or stop phase timing of histogram and
+    pipeline calls."""
+    _check(_lib.sinet_timing_enable(int(bool(on))), "sinet_timing_enable")
+
+
+def timing_read() -> dict:
+    """Device ms per phase summed over the calls timed since timing_enable."""
+    t = Timing()
+    _check(_lib.sinet_timing_read(ctypes.byref(t)), "sinet_timing_read")
+    return {name: getattr(t, name) for name, _ in Timing._fields_}
 
 
 # host <-> device helpers for uint32/uint64 data held in signed tensors

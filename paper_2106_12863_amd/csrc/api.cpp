@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "sinet.h"
+#include "inout_index.h"
 #include "sinet_internal.h"
 
 namespace sinet {
@@ -111,72 +112,21 @@ static void build_trie(const std::vector<uint32_t>& B, std::vector<uint32_t>& tr
     }
 }
 
-// In/out index over the union of all prefixes (label-only queries).  The
-// union's boundaries U are the points where membership changes.  A /16
-// block no boundary of U cuts is wholly in or out (2-bit state 1 / 0);
-// a cut block (state 2) gets an ordinal r, its membership at the block start
-// and the sorted low 16 bits of the boundaries inside it: an address is in
-// iff the start state differs from the parity of the boundaries <= its low
-// 16 bits.  Layout (32-bit words): filter[4096] | rank[4096] u16 (cut blocks
-// before each filter word) | start[M + 1] u16 | start bits[M] | list[T] u16.
-// Returns false when the ordinals or offsets would not fit 16 bits.
+// In/out index of the union of the prefixes (layout in inout_index.h).
 static bool build_inout(const std::vector<uint32_t>& B, const std::vector<uint32_t>& owner,
                         std::vector<uint32_t>& io, DevTable& d) {
-    std::vector<uint32_t> U;
+    std::vector<uint32_t> U;  // where membership of the union changes
     bool prev = false;
     for (size_t j = 0; j < B.size(); ++j) {
         const bool in = owner[j] != 0;
         if (in != prev) U.push_back(B[j]);
         prev = in;
     }
-    std::vector<uint32_t> filt(kFilterWords, 0);
-    std::vector<uint32_t> rank(kFilterWords, 0), start, sbit, list;
-    size_t u = 0;
-    bool state = false;
-    uint32_t mixed = 0;
-    for (uint64_t k = 0; k < 65536; ++k) {
-        if ((k & 15) == 0) rank[k >> 4] = mixed;
-        const uint64_t base = k << 16;
-        while (u < U.size() && U[u] == base) {
-            state = !state;
-            ++u;
-        }
-        const bool s0 = state;
-        const size_t u0 = u;
-        while (u < U.size() && ((uint64_t)U[u] >> 16) == k) {
-            state = !state;
-            ++u;
-        }
-        uint32_t st = s0 ? 1u : 0u;
-        if (u != u0) {
-            st = 2;
-            start.push_back((uint32_t)list.size());
-            sbit.push_back(s0 ? 1u : 0u);
-            for (size_t v = u0; v < u; ++v) list.push_back(U[v] & 0xFFFFu);
-            ++mixed;
-        }
-        filt[k >> 4] |= st << ((k & 15) * 2);
-    }
-    start.push_back((uint32_t)list.size());
-    if (mixed + 1 > 65535 || list.size() > 65535) return false;
-    auto pack16 = [](const std::vector<uint32_t>& v, std::vector<uint32_t>& out) {
-        for (size_t i = 0; i < v.size(); i += 2)
-            out.push_back((v[i] & 0xFFFFu) | (i + 1 < v.size() ? (v[i + 1] & 0xFFFFu) << 16 : 0u));
-    };
-    io.assign(filt.begin(), filt.end());
-    d.io_rank = (uint32_t)io.size();
-    pack16(rank, io);
-    d.io_start = (uint32_t)io.size();
-    pack16(start, io);
-    d.io_sbit = (uint32_t)io.size();
-    for (uint32_t r = 0; r < mixed; r += 32) {
-        uint32_t w = 0;
-        for (uint32_t b = 0; b < 32 && r + b < mixed; ++b) w |= sbit[r + b] << b;
-        io.push_back(w);
-    }
-    d.io_list = (uint32_t)io.size();
-    pack16(list, io);
-    d.io_words = (uint32_t)io.size();
+    IoLayout lay{};
+    if (!build_inout_index(U, io, lay)) return false;
+    d.io_words = lay.words;
+    d.io_slot = lay.slot;
+    d.io_list = lay.list;
     return true;
 }
 
@@ -286,7 +236,8 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     if (n_prefix == 0) return fail(SINET_ERR_INVALID_ARG, "n_prefix is 0");
     if (n_prefix > SINET_MAX_PREFIXES) return fail(SINET_ERR_INVALID_ARG, "too many prefixes");
     const bool want_io = (kind & SINET_TABLE_NO_INOUT_INDEX) == 0;
-    kind = (sinet_lookup)(kind & ~SINET_TABLE_NO_INOUT_INDEX);
+    const bool global_bsearch = (kind & SINET_TABLE_GLOBAL_BSEARCH) != 0;
+    kind = (sinet_lookup)(kind & ~(SINET_TABLE_NO_INOUT_INDEX | SINET_TABLE_GLOBAL_BSEARCH));
     if (kind == SINET_LOOKUP_AUTO) kind = n_prefix <= 64 ? SINET_LOOKUP_SCAN : SINET_LOOKUP_BSEARCH;
     if (kind < SINET_LOOKUP_SCAN || kind > SINET_LOOKUP_LEARNED_MLP)
         return fail(SINET_ERR_INVALID_ARG, "unknown lookup kind");
@@ -327,8 +278,9 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
         (mw <= kLdsMemberMaxWords && fw + mw + 1024 + kLdsReserveWords <= lds_words) ? mw : 0;
     // learned kinds keep fewer sampled boundaries, leaving LDS for the model
     const bool learned_kind = kind == SINET_LOOKUP_LEARNED_PLA || kind == SINET_LOOKUP_LEARNED_MLP;
-    const uint32_t top_cap = std::min<uint32_t>(learned_kind ? kLdsTopMax / 2 : kLdsTopMax,
-                                                lds_words - fw - member_lds - kLdsReserveWords);
+    uint32_t top_cap = std::min<uint32_t>(learned_kind ? kLdsTopMax / 2 : kLdsTopMax,
+                                          lds_words - fw - member_lds - kLdsReserveWords);
+    if (global_bsearch && kind == SINET_LOOKUP_BSEARCH) top_cap = 1;  // one leaf: all of B
     uint32_t top_log2 = 0;
     while (((uint64_t)m + (1ull << top_log2) - 1) >> top_log2 > top_cap) ++top_log2;
     const uint32_t n_top = (uint32_t)(((uint64_t)m + (1ull << top_log2) - 1) >> top_log2);
@@ -421,9 +373,7 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     if (io_ok) {
         d.io = (const uint32_t*)(a + oIo);
         d.io_words = iod.io_words;
-        d.io_rank = iod.io_rank;
-        d.io_start = iod.io_start;
-        d.io_sbit = iod.io_sbit;
+        d.io_slot = iod.io_slot;
         d.io_list = iod.io_list;
     }
     d.m_f = (float)m;
@@ -665,6 +615,24 @@ sinet_status sinet_mlp_loss_grad(const float* params, const float* x, const floa
         return fail(SINET_ERR_INVALID_ARG, "NULL argument");
     if (n == 0) return fail(SINET_ERR_INVALID_ARG, "n is 0");
     return mlp_loss_grad(params, x, y, n, loss, grad, stream);
+}
+
+sinet_status sinet_timing_enable(int on) { return timing_enable(on); }
+
+sinet_status sinet_timing_read(sinet_timing* out) {
+    if (!out) return fail(SINET_ERR_INVALID_ARG, "out is NULL");
+    double ms[PH_COUNT];
+    uint64_t calls = 0, launches = 0;
+    const sinet_status st = timing_read(ms, &calls, &launches);
+    if (st != SINET_OK) return st;
+    out->lookup_ms = ms[PH_LOOKUP];
+    out->stage1_ms = ms[PH_STAGE1];
+    out->index_ms = ms[PH_INDEX];
+    out->stage2_ms = ms[PH_STAGE2];
+    out->far_ms = ms[PH_FAR];
+    out->calls = calls;
+    out->stage1_launches = launches;
+    return SINET_OK;
 }
 
 }  // extern "C"

@@ -33,7 +33,9 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
+#include "inout_index.h"
 #include "sinet_device.h"
 #include "sinet_internal.h"
 
@@ -244,37 +246,13 @@ __device__ __forceinline__ uint32_t u16_at(const uint32_t* w, uint32_t i) {
     return (w[i >> 1] >> ((i & 1u) * 16)) & 0xFFFFu;
 }
 
-// Membership of a in the union of the prefixes, from the in/out index (LDS).
-__device__ __forceinline__ uint32_t inout_of(const DevTable& t, const uint32_t* io, uint32_t a) {
-    const uint32_t k = a >> 16;
-    const uint32_t f = io[k >> 4];
-    const uint32_t sh = (k & 15u) * 2;
-    const uint32_t st = (f >> sh) & 3u;
-    if (st < 2u) return st;
-    const uint32_t cut = (f >> 1) & ~f & 0x55555555u;  // bit 2i: block i of the word is cut
-    const uint32_t r = u16_at(io + t.io_rank, k >> 4) + __popc(cut & ((1u << sh) - 1u));
-    uint32_t lo = u16_at(io + t.io_start, r);
-    uint32_t hi = u16_at(io + t.io_start, r + 1);
-    const uint32_t first = lo;
-    const uint32_t low = a & 0xFFFFu;
-    while (lo < hi) {  // number of boundaries <= low
-        const uint32_t mid = (lo + hi) >> 1;
-        if (u16_at(io + t.io_list, mid) <= low) lo = mid + 1;
-        else hi = mid;
-    }
-    const uint32_t s0 = (io[t.io_sbit + (r >> 5)] >> (r & 31u)) & 1u;
-    return s0 ^ ((lo - first) & 1u);
-}
-
 template <uint32_t KIND, int N>
 __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, const uint32_t* a,
                                         bool want_code, uint32_t* in, uint32_t* code) {
     if constexpr (KIND == KK_INOUT) {
+        inout_lookup<N>(v.io, t.io_slot, t.io_list, a, in);
 #pragma unroll
-        for (int q = 0; q < N; ++q) {
-            in[q] = inout_of(t, v.io, a[q]);
-            code[q] = 0;
-        }
+        for (int q = 0; q < N; ++q) code[q] = 0;
     } else if constexpr (KIND == KK_SCAN) {
 #pragma unroll
         for (int q = 0; q < N; ++q) {
@@ -557,7 +535,7 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) 
 // ---------------------------------------------------------------------------
 template <uint32_t KIND, int HM, bool VEC>
 __global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint32_t used = 0;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
     PrivHist h{nullptr, nullptr};
@@ -677,9 +655,22 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
 // the byte count itself when < 2^19, else an index into the chunk's
 // 64-bit big-value slots.
 // ---------------------------------------------------------------------------
+// Minimum over the 64 lanes of a wave by DPP row shifts and row broadcasts
+// (lanes a row shift or a masked row leaves without a source keep ~0, the
+// identity of min); lane 63 ends with the result.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t x) {
+    return min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, CTRL, ROW_MASK, 0xF,
+                                                         false));
+}
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-    for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o));
-    return x;
+    x = dpp_min_step<0x111, 0xF>(x);  // row_shr:1
+    x = dpp_min_step<0x112, 0xF>(x);  // row_shr:2
+    x = dpp_min_step<0x114, 0xF>(x);  // row_shr:4
+    x = dpp_min_step<0x118, 0xF>(x);  // row_shr:8
+    x = dpp_min_step<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x = dpp_min_step<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 // Raw column words of one lane's four sessions (loaded one chunk ahead).
@@ -708,15 +699,19 @@ struct Stage1Shared {
     uint32_t base[kWin];
     uint32_t far[kChunk / 32];
     uint32_t wmin[kStage1Block / 64];
-    uint32_t nbig, nfar, bmin;
+    uint32_t nbig, nfar;
 };
+// Static LDS of a stage-1 workgroup: two alternating Stage1Shared and the
+// record buffer (one suffices: a chunk fills it only after its first barrier,
+// which every lane reaches after copying the previous chunk out).
+constexpr size_t kStage1StaticLds = 2 * sizeof(Stage1Shared) + sizeof(uint4) * (kChunk / 4);
 
 // Stage 1 on one chunk.  c is the chunk within the stream (sessions
 // c * kChunk + ...), g its index in the workspace (slots, directory, far
 // bits) and b0 the workspace index of the stream's first block.
 template <uint32_t KIND>
 __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& w, const LdsView& v,
-                                             Stage1Shared& sh, uint64_t c, uint64_t g, uint32_t b0,
+                                             Stage1Shared& sh, uint4* srec, uint64_t c, uint64_t g, uint32_t b0,
                                              const Raw4& cur, bool full, Dropped& d) {
     const uint32_t tid = threadIdx.x;
     const uint64_t i0 = c * kChunk + (uint64_t)tid * 4;
@@ -758,6 +753,8 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
         if (inw[k]) mymin = min(mymin, blk[k]);
         else if (i0 + k < p.n) d.add(lab[k], by[k]);
     }
+    // sh alternates between two buffers from chunk to chunk, so clearing this
+    // chunk's counters cannot race with lanes still writing the previous one
     mymin = wave_min(mymin);
     if ((tid & 63) == 0) sh.wmin[tid >> 6] = mymin;
     if (tid < kWin) sh.cnt[tid] = 0;
@@ -767,13 +764,9 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
         sh.nfar = 0;
     }
     __syncthreads();
-    if (tid < 64) {
-        uint32_t m = tid < kStage1Block / 64 ? sh.wmin[tid] : 0xFFFFFFFFu;
-        m = wave_min(m);
-        if (tid == 0) sh.bmin = m;
-    }
-    __syncthreads();
-    const uint32_t bmin = sh.bmin;
+    uint32_t bmin = 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < kStage1Block / 64; ++k) bmin = min(bmin, sh.wmin[k]);
     uint32_t rank[4], bigi[4];
     bool loc[4];
 #pragma unroll
@@ -813,7 +806,7 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
         if (tid == 0) w.nd[g] = (uint32_t)__popcll(m);
     }
     __syncthreads();
-    const uint64_t slot0 = g * kChunk;
+    uint32_t* lrec = reinterpret_cast<uint32_t*>(srec);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (!loc[k]) continue;
@@ -826,25 +819,32 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
         } else {
             rec |= (uint32_t)by[k];
         }
-        w.rec[slot0 + sh.base[r] + rank[k]] = rec;
+        lrec[sh.base[r] + rank[k]] = rec;
+    }
+    __syncthreads();
+    {   // the filled slots of the chunk, one 16-byte store per lane
+        const uint32_t nloc = sh.base[kWin - 1] + sh.cnt[kWin - 1];
+        uint4* dst = reinterpret_cast<uint4*>(w.rec + g * kChunk);
+        for (uint32_t k = tid; k < (nloc + 3) / 4; k += kStage1Block) dst[k] = srec[k];
     }
     if (sh.nfar) {
         for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block)
             w.farbits[g * (kChunk / 32) + k] = sh.far[k];
         if (tid == 0) w.farlist[atomicAdd(w.farcount, 1u)] = (uint32_t)g;
     }
-    __syncthreads();
 }
 
 template <uint32_t KIND>
-__global__ void __launch_bounds__(kStage1Block) k_stage1(PassParams p, PartWs w) {
-    extern __shared__ uint32_t lds[];
-    __shared__ Stage1Shared sh;
+__global__ void __launch_bounds__(kStage1Block, 4) k_stage1(PassParams p, PartWs w) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ Stage1Shared sh[2];
+    __shared__ uint4 srec[kChunk / 4];
     uint32_t used = 0;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
     Dropped d{};
     const uint32_t tid = threadIdx.x;
     const uint64_t n_chunks = w.n_chunks;
+    uint32_t iter = 0;
     // a chunk is "full" when its 4096 sessions exist and vector loads are allowed
     auto full = [&](uint64_t c) { return w.vec && (c + 1) * kChunk <= p.n; };
     Raw4 cur{}, nxt{};
@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(kStage1Block) k_stage1(PassParams p, PartWs w)
     for (; c < n_chunks; c += gridDim.x) {
         const uint64_t cn = c + gridDim.x;
         if (cn < n_chunks && full(cn)) load4<KIND>(p, cn * kChunk + (uint64_t)tid * 4, nxt);
-        stage1_chunk<KIND>(p, w, v, sh, c, c, 0u, cur, full(c), d);
+        stage1_chunk<KIND>(p, w, v, sh[iter++ & 1u], srec, c, c, 0u, cur, full(c), d);
         cur = nxt;
     }
     d.flush(p.dropped);
@@ -1099,28 +1099,37 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
 }
 
 template <uint32_t KIND>
-__global__ void __launch_bounds__(kStage1Block) k_batch_stage1(BatchArgs a, PartWs w) {
-    extern __shared__ uint32_t lds[];
-    __shared__ Stage1Shared sh;
+__device__ __forceinline__ void batch_stage1(const BatchArgs& a, const PartWs& w) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ Stage1Shared sh[2];
+    __shared__ uint4 srec[kChunk / 4];
     __shared__ uint32_t s_item;
+    __shared__ BatchStreamDev s_bs;  // the current stream's descriptor
     const uint32_t tid = threadIdx.x;
     uint32_t staged = 0xFFFFFFFFu;
     LdsView v{};
     uint32_t used = 0;
+    uint32_t iter = 0;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(a.counter, 1u);
         __syncthreads();
         const uint32_t it = uniform_u32(s_item);
-        __syncthreads();
         if (it >= a.n_items) break;
         const uint4 item = a.items[it];
         const uint32_t si = uniform_u32(item.x);
-        const BatchStreamDev& bs = a.streams[si];
-        const PassParams& p = bs.p;
         if (si != staged) {
-            v = stage_lds<KIND>(p.t, lds, &used);  // ends with a barrier
+            // descriptor to LDS (read there by every lane, never from global
+            // memory inside the session loop), then the table
+            constexpr uint32_t kWords = sizeof(BatchStreamDev) / 4;
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(a.streams + si);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&s_bs);
+            for (uint32_t k = tid; k < kWords; k += blockDim.x) dst[k] = src[k];
+            __syncthreads();
+            v = stage_lds<KIND>(s_bs.p.t, lds, &used);  // ends with a barrier
             staged = si;
         }
+        const BatchStreamDev& bs = s_bs;
+        const PassParams& p = bs.p;
         Dropped d{};
         if (bs.priv) {
             PrivHist h;
@@ -1160,7 +1169,8 @@ __global__ void __launch_bounds__(kStage1Block) k_batch_stage1(BatchArgs a, Part
             if (c < item.z && full(c)) load4<KIND>(p, c * kChunk + (uint64_t)tid * 4, cur);
             for (; c < item.z; ++c) {
                 if (c + 1 < item.z && full(c + 1)) load4<KIND>(p, (c + 1) * kChunk + (uint64_t)tid * 4, nxt);
-                stage1_chunk<KIND>(p, w, v, sh, c, bs.chunk0 + c, bs.block0, cur, full(c), d);
+                stage1_chunk<KIND>(p, w, v, sh[iter++ & 1u], srec, c, bs.chunk0 + c, bs.block0, cur,
+                                   full(c), d);
                 cur = nxt;
             }
         }
@@ -1184,9 +1194,21 @@ __global__ void __launch_bounds__(kStage2Block) k_batch_stage2(BatchArgs a, Part
     stage2_block(w, sh, gb, gb - bs.block0, bs.p.count, bs.p.hbytes, bs.p.n_bins, 0);
 }
 
+
+// In/out-index lookups fit 128 VGPRs (4 waves per SIMD, two workgroups per CU);
+// the interval kinds keep their registers rather than spill.
+template <uint32_t KIND>
+__global__ void __launch_bounds__(kStage1Block) k_batch_stage1(BatchArgs a, PartWs w) {
+    batch_stage1<KIND>(a, w);
+}
+template <uint32_t KIND>
+__global__ void __launch_bounds__(kStage1Block, 4) k_batch_stage1_o4(BatchArgs a, PartWs w) {
+    batch_stage1<KIND>(a, w);
+}
+
 template <uint32_t KIND>
 __global__ void __launch_bounds__(kMaxBlock) k_batch_far(BatchArgs a, PartWs w) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint32_t staged = 0xFFFFFFFFu;
     LdsView v{};
     uint32_t used = 0;
@@ -1423,6 +1445,93 @@ sinet_status launch_scan_fill(const PartWs& w, hipStream_t s) {
     return check_hip(hipGetLastError(), "segment index launch");
 }
 
+// ---- phase timing ------------------------------------------------------------
+// While enabled, every phase of run_hist is bracketed by two events recorded on
+// the launch stream; they are read (and destroyed) by timing_read.
+namespace {
+struct Mark {
+    int phase;
+    hipEvent_t a, b;
+};
+std::mutex g_tm_mu;
+bool g_tm_on = false;
+std::vector<Mark> g_tm_marks;
+uint64_t g_tm_calls = 0;
+
+class PhaseScope {
+   public:
+    PhaseScope(int phase, hipStream_t s) : phase_(phase), s_(s) {
+        {
+            std::lock_guard<std::mutex> g(g_tm_mu);
+            if (!g_tm_on) return;
+        }
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        if (hipEventCreate(&a_) != hipSuccess) return;
+        if (hipEventCreate(&b_) != hipSuccess) {
+            (void)hipEventDestroy(a_);
+            return;
+        }
+        on_ = hipEventRecord(a_, s) == hipSuccess;
+        if (!on_) {
+            (void)hipEventDestroy(a_);
+            (void)hipEventDestroy(b_);
+        }
+    }
+    ~PhaseScope() {
+        if (!on_) return;
+        (void)hipEventRecord(b_, s_);
+        std::lock_guard<std::mutex> g(g_tm_mu);
+        g_tm_marks.push_back(Mark{phase_, a_, b_});
+    }
+    PhaseScope(const PhaseScope&) = delete;
+    PhaseScope& operator=(const PhaseScope&) = delete;
+
+   private:
+    int phase_;
+    hipStream_t s_;
+    hipEvent_t a_{}, b_{};
+    bool on_ = false;
+};
+
+void count_timed_call() {
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    if (g_tm_on) ++g_tm_calls;
+}
+
+void drop_marks_locked() {
+    for (const Mark& m : g_tm_marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    g_tm_marks.clear();
+    g_tm_calls = 0;
+}
+}  // namespace
+
+sinet_status timing_enable(int on) {
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    if (on) drop_marks_locked();
+    g_tm_on = on != 0;
+    return SINET_OK;
+}
+
+sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches) {
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    for (int k = 0; k < PH_COUNT; ++k) ms[k] = 0.0;
+    *stage1_launches = 0;
+    for (const Mark& m : g_tm_marks) {
+        float t = 0.f;
+        sinet_status st = check_hip(hipEventSynchronize(m.b), "timing event");
+        if (st == SINET_OK) st = check_hip(hipEventElapsedTime(&t, m.a, m.b), "timing event");
+        if (st != SINET_OK) return st;
+        ms[m.phase] += t;
+        if (m.phase == PH_STAGE1) ++*stage1_launches;
+    }
+    *calls = g_tm_calls;
+    return SINET_OK;
+}
+
 // Histogram of one stream by the partitioned path (workspace given).
 sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& w, int accumulate,
                              hipStream_t s) {
@@ -1435,19 +1544,29 @@ sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& 
     if (st != SINET_OK) return st;
     Stage1Fn f1 = pick_stage1(kind);
     const size_t lds = (kind == KK_LABEL_IN ? 0 : p.t.lds_bytes) + 8;
-    if (lds + 4096 > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
+    if (lds + kStage1StaticLds > 160 * 1024)
+        return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
     uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)f1, kStage1Block, lds);
     if (grid > w.n_chunks) grid = w.n_chunks;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(f1, dim3((unsigned)grid), dim3(kStage1Block), lds, s, p, wv);
-    st = check_hip(hipGetLastError(), "stage-1 launch");
+    {
+        PhaseScope ph(PH_STAGE1, s);
+        hipLaunchKernelGGL(f1, dim3((unsigned)grid), dim3(kStage1Block), lds, s, p, wv);
+        st = check_hip(hipGetLastError(), "stage-1 launch");
+    }
     if (st != SINET_OK) return st;
     const uint32_t nb = w.n_blocks;
-    st = launch_scan_fill(wv, s);
+    {
+        PhaseScope ph(PH_INDEX, s);
+        st = launch_scan_fill(wv, s);
+    }
     if (st != SINET_OK) return st;
-    hipLaunchKernelGGL(k_stage2, dim3(nb), dim3(kStage2Block), 0, s, wv, p.count, p.hbytes,
-                       p.n_bins, accumulate);
-    st = check_hip(hipGetLastError(), "stage-2 launch");
+    {
+        PhaseScope ph(PH_STAGE2, s);
+        hipLaunchKernelGGL(k_stage2, dim3(nb), dim3(kStage2Block), 0, s, wv, p.count, p.hbytes,
+                           p.n_bins, accumulate);
+        st = check_hip(hipGetLastError(), "stage-2 launch");
+    }
     if (st != SINET_OK) return st;
     // far sessions: labels are already stored, do not store them twice
     FarList far{w.farlist, w.farcount, w.farbits};
@@ -1456,6 +1575,7 @@ sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& 
     q.src_inst = nullptr;
     q.dst_inst = nullptr;
     q.dropped = nullptr;
+    PhaseScope ph(PH_FAR, s);
     return launch_k_pass(q, kind, H_ATOMIC, false, far, 0, s);
 }
 
@@ -1469,7 +1589,7 @@ static BatchFn pick_batch_stage1(uint32_t kind) {
         case KK_TRIE: return k_batch_stage1<KK_TRIE>;
         case KK_PLA: return k_batch_stage1<KK_PLA>;
         case KK_MLP: return k_batch_stage1<KK_MLP>;
-        case KK_INOUT: return k_batch_stage1<KK_INOUT>;
+        case KK_INOUT: return k_batch_stage1_o4<KK_INOUT>;
         default: return nullptr;
     }
 }
@@ -1495,7 +1615,8 @@ sinet_status launch_batch_stage1(uint32_t kind, const BatchArgs& a, const PartWs
                                  uint32_t grid, hipStream_t s) {
     BatchFn fn = pick_batch_stage1(kind);
     if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no batch kernel for this lookup kind");
-    if (lds > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "batch needs more LDS than a CU has");
+    if (lds + kStage1StaticLds + sizeof(BatchStreamDev) + 16 > 160 * 1024)
+        return fail(SINET_ERR_UNSUPPORTED, "batch needs more LDS than a CU has");
     if (grid == 0) grid = device_cu_count() * blocks_per_cu((const void*)fn, kStage1Block, lds);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kStage1Block), lds, s, a, w);
     return check_hip(hipGetLastError(), "batch stage-1 launch");
@@ -1572,6 +1693,7 @@ int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n)
 sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s) {
     const uint32_t kind = (mode & PASS_LABEL_IN) ? (uint32_t)KK_LABEL_IN : p.t.kind;
     if (p.n == 0) return SINET_OK;
+    count_timed_call();
     const int strat = hist_strategy(p.t, kind, p.n_bins, p.n);
     if (strat == H_PRIVATE) {
         sinet_status st = SINET_OK;
@@ -1581,6 +1703,7 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
             if (st != SINET_OK) return st;
         }
         FarList none{};
+        PhaseScope ph(PH_STAGE1, s);
         return launch_k_pass(p, kind, H_PRIVATE, vector_ok(p, kind, true), none,
                              12ull * 4 * p.n_bins + 8, s);
     }
@@ -1616,6 +1739,7 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
             if (!lq.label_out) lq.label_out = (uint8_t*)ws + wsb;
             lq.pos_out = nullptr;
             FarList none{};
+            PhaseScope ph(PH_LOOKUP, s);
             st = launch_k_pass(lq, kind, H_NONE, vector_ok(lq, kind, false), none, 0, s);
             q.label_in = lq.label_out;
             q.label_out = nullptr;

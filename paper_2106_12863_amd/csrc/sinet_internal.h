@@ -50,10 +50,8 @@ struct DevTable {
     // in/out index (label-only queries): word offsets inside io[]
     const uint32_t* io;         // [io_words] or nullptr
     uint32_t io_words;
-    uint32_t io_rank;           // u16 pairs: mixed blocks before each filter word
-    uint32_t io_start;          // u16 pairs: first boundary of each mixed block (M + 1)
-    uint32_t io_sbit;           // bits: membership at the start of each mixed block
-    uint32_t io_list;           // u16 pairs: boundary offsets inside mixed blocks
+    uint32_t io_slot;           // per cut /16 block: up to four boundary offsets
+    uint32_t io_list;           // overflow list of blocks with more boundaries
     uint32_t max_err;
     float m_f;                  // (float) m
     unsigned long long* fallbacks;  // device counter
@@ -189,6 +187,10 @@ sinet_status launch_pass(const PassParams& p, uint32_t mode, hipStream_t s);
 sinet_status launch_zero(unsigned long long* p, uint64_t n_words, hipStream_t s);
 // histogram passes (labels computed or given) with the strategy chosen per window
 sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s);
+// phase timing of run_hist (event pairs on the launch stream)
+enum TimedPhase { PH_LOOKUP = 0, PH_STAGE1, PH_INDEX, PH_STAGE2, PH_FAR, PH_COUNT };
+sinet_status timing_enable(int on);
+sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches);
 size_t part_ws_bytes(uint64_t n, uint32_t n_bins);
 PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins);
 sinet_status run_partitioned(const PassParams& p, uint32_t kind, const PartWs& w, int accumulate,

@@ -125,6 +125,38 @@ def test_pipeline_day_shape_full_bins(sinet, torch):
         del out
 
 
+def test_phase_timing_counts_calls_and_keeps_results(sinet, torch):
+    """Timed calls record their phases and compute the same histogram."""
+    wl = sinetgen.config(2, n=1_000_003)
+    s = sinetgen.sessions(wl)
+    ts, src, dst, nb = _up(sinet, s)
+    w = wl.window
+    elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"], s["bytes"],
+                                       w.t0, w.width, w.n_bins)
+    tab = sinet.Table(wl.pbase, wl.plen, kind="trie", inout_index=False)  # separate lookup pass
+    sinet.timing_enable(True)
+    try:
+        for _ in range(2):
+            lab, out = sinet.pipeline(tab, ts, src, dst, nb, w.t0, w.width, w.n_bins)
+            assert np.array_equal(lab.cpu().numpy(), elab)
+            _cmp_hist(sinet, out, (ec, eb, ed))
+            del out
+        # a small window takes the private-histogram pass (stage-1 phase only)
+        sinet.pipeline(tab, ts, src, dst, nb, w.t0, 60_000, 1441)
+        t = sinet.timing_read()
+    finally:
+        sinet.timing_enable(False)
+    _say("timing", t)
+    assert t["calls"] == 3 and t["stage1_launches"] == 3
+    for k in ("lookup_ms", "stage1_ms", "index_ms", "stage2_ms"):
+        assert t[k] > 0.0, k
+    sinet.pipeline(tab, ts, src, dst, nb, w.t0, w.width, w.n_bins)
+    sinet.timing_enable(True)
+    t2 = sinet.timing_read()
+    sinet.timing_enable(False)
+    assert t2["calls"] == 0 and t2["stage1_ms"] == 0.0
+
+
 # ------------------------------------------------------------ discrimination
 @pytest.mark.parametrize("kind", ["scan", "bsearch", "trie"])
 def test_discriminate_institutions(sinet, torch, kind):
@@ -229,6 +261,43 @@ def test_edge_tables_and_ragged_sizes(sinet, torch, kind):
             assert np.array_equal(sinet.to_host_u32(di), edi)
 
 
+def _dense_tables():
+    """Tables whose union cuts /16 blocks many times: /24s and /28s packed in
+    two blocks (more than four boundaries per block), single hosts at block
+    offsets 5, 9 and 0xFFFF, and 3000 random hosts."""
+    rng = np.random.default_rng(11)
+    b = ([0x0A000000 + (i << 8) for i in range(0, 200, 3)] +
+         [0x0A010000 + (i << 4) for i in range(0, 4000, 7)] +
+         [0x0A020005, 0x0A020009, 0x0A02FFFF, 0x0A030000, 0x0A04FFFF])
+    l = [24] * 67 + [28] * len(range(0, 4000, 7)) + [32, 32, 32, 32, 32]
+    hosts = rng.integers(0, 1 << 32, 3000, dtype=np.uint64).astype(np.uint32)
+    return [(np.array(b, np.uint32), np.array(l, np.uint8)),
+            (hosts, np.full(3000, 32, np.uint8))]
+
+
+def test_inout_index_dense_blocks(sinet, torch):
+    """Label-only lookups through the in/out index at every union boundary
+    and its neighbours, at block edges and at random addresses."""
+    rng = np.random.default_rng(12)
+    for b, l in _dense_tables():
+        B, own = oracle.endpoints(b, l)
+        inn = (own != 0).astype(np.int8)
+        U = B[np.concatenate([[inn[0] == 1], inn[1:] != inn[:-1]])].astype(np.int64)
+        near = (U[:, None] + np.arange(-2, 3)[None, :]).ravel() % (1 << 32)
+        blocks = np.unique(U >> 16)
+        edges = np.concatenate([blocks << 16, (blocks << 16) | 0xFFFF, (blocks << 16) | 0x7FFF])
+        rand = rng.integers(0, 1 << 32, 200_003, dtype=np.uint64)
+        src = np.concatenate([near, edges, rand]).astype(np.uint32)
+        dst = rng.permutation(src)
+        tab = sinet.Table(b, l, kind="bsearch")
+        assert tab.info().inout_index == 1
+        S, D = sinet.to_device_u32(src), sinet.to_device_u32(dst)
+        lab, _, _ = sinet.discriminate(tab, S, D)
+        torch.cuda.synchronize()
+        elab, _, _ = oracle.classify(b, l, src, dst)
+        assert np.array_equal(lab.cpu().numpy(), elab)
+
+
 def test_empty_input_clears_or_keeps(sinet, torch):
     b, l = _edge_table()
     tab = sinet.Table(b, l, kind="bsearch")
@@ -267,9 +336,10 @@ def test_intervals_and_positions(sinet, torch, cfg):
     q = np.concatenate([B, hi, rng.integers(0, 1 << 32, 200_001, dtype=np.uint64).astype(np.uint32)])
     expect = learned.positions(B, q)
     qd = sinet.to_device_u32(q)
-    kinds = ["bsearch", "trie", "pla", "mlp"] + (["scan"] if wl.n_prefix <= 1024 else [])
+    kinds = ["bsearch", "bsearch_global", "trie", "pla", "mlp"] + (["scan"] if wl.n_prefix <= 1024 else [])
     for kind in kinds:
-        tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
+        tab = sinet.Table(wl.pbase, wl.plen, kind=kind.replace("_global", ""),
+                          global_bsearch=kind.endswith("_global"))
         gB, gown = tab.intervals()
         assert np.array_equal(gB, B) and np.array_equal(gown, own), kind
         modes = [{}]
@@ -357,7 +427,8 @@ def test_mlp_gradients_vs_oracle(sinet, torch):
 
 
 @pytest.mark.parametrize("kind,inout", [("pla", False), ("mlp", False), ("pla", True),
-                                        ("bsearch", False), ("trie", False)])
+                                        ("bsearch", False), ("bsearch_global", False),
+                                        ("trie", False)])
 def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, inout):
     """The 200,000-prefix clustered table: labels and histograms of every
     kind, with the kind's own search (in/out index off) and with the index."""
@@ -365,7 +436,8 @@ def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, in
     _say("large table", kind, inout)
     s = sinetgen.sessions(wl, start=0, stop=wl.n)
     ts, src, dst, nb = _up(sinet, s)
-    tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=inout)
+    tab = sinet.Table(wl.pbase, wl.plen, kind=kind.replace("_global", ""), inout_index=inout,
+                      global_bsearch=kind.endswith("_global"))
     assert tab.info().inout_index == int(inout)
     if kind not in ("pla", "mlp"):
         w = wl.window
