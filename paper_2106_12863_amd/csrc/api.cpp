@@ -29,7 +29,7 @@ sinet_status check_hip(hipError_t e, const char* what) {
 
 static constexpr uint32_t kLdsTopMax = 16384;        // sampled boundaries kept in LDS
 static constexpr uint32_t kLdsMemberMaxWords = 16384; // membership bits kept in LDS
-static constexpr uint32_t kLdsReserveWords = 3072;    // static LDS of the pass kernels
+static constexpr uint32_t kLdsReserveWords = 3328;    // static LDS of the pass kernels
 static constexpr uint32_t kMaxSegments = 65535;       // PLA segment index fits 16 bits
 
 static uint32_t prefix_mask(uint32_t z) {

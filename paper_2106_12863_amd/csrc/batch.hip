@@ -106,7 +106,7 @@ sinet_status prepare(const sinet_stream* st, uint32_t ns, Prepared& pr) {
     }
     pr.chunk_base[ns] = c;
     pr.block_base[ns] = (uint32_t)k;
-    if (c * kChunk >= (1ull << 32) || k >= (1ull << 31))
+    if (c * kChunkSlots >= (1ull << 32) || k >= (1ull << 31))
         return fail(SINET_ERR_UNSUPPORTED, "batch too large for one plan (split it)");
     pr.c_tot = c;
     pr.k_tot = (uint32_t)k;

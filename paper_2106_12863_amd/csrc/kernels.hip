@@ -54,8 +54,8 @@ enum KernelKind : uint32_t {
 constexpr int kXcds = 8;
 constexpr int kMaxBlock = 1024;
 constexpr int kStage2Block = 512;
-constexpr int kSegBatch = kStage2Block;    // segments staged per stage-2 round
-constexpr int kRecUnroll = 4;              // independent record loads per stage-2 lane
+constexpr int kSegMax = 256;               // segment descriptors of a block held in LDS
+constexpr int kRecUnroll = 8;              // independent record loads per stage-2 lane
 constexpr uint32_t kSmallMax = 1u << 19;  // byte counts stored inline in a record
 constexpr uint64_t kMaxPiece = 1ull << 31;  // sessions per partitioned pass (32-bit slots)
 
@@ -639,21 +639,27 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
 // (block = bin / kBlockBins, offset, label).  Sessions are counting-sorted in
 // LDS by block relative to the chunk's first block (a window of kWin blocks)
 // and written as 4-byte records, grouped by block, into the chunk's own slot
-// range; the chunk's directory lists (block, first slot, count) for every
+// range (every block's segment padded with null records to whole 16-byte
+// groups); the chunk's directory lists (block, first slot, slots) for every
 // block it touched.  Near time-sorted input (the paper's session logs)
 // touches few blocks per chunk.
 // Segment index: per-block directory counts, an exclusive scan, and a fill
 // that groups the directory entries by block (k_fill).
-// Stage 2 (k_stage2): one workgroup per block accumulates its segments'
-// records in LDS and writes the block's count and byte bins once, with
-// coalesced stores; no zero-fill and no global atomics.
+// Stage 2 (k_stage2): persistent workgroups take blocks in turn, accumulate a
+// block's segments' records in LDS and write the block's count and byte bins
+// once, with coalesced stores, while the next block's segment list is in
+// flight; no zero-fill and no global atomics.
 // Far path: a session outside its chunk's block window, with bytes >= 2^52,
-// or beyond the chunk's big-value slots is flagged and merged afterwards by
-// k_pass<H_ATOMIC> with global atomics, so any input stays exact.
+// or beyond the chunk's extra record slots is flagged and merged afterwards
+// by k_pass<H_ATOMIC> with global atomics, so any input stays exact.
 //
-// Record: label (2 bits) | offset in block (10) | big flag (1) | payload (19):
-// the byte count itself when < 2^19, else an index into the chunk's
-// 64-bit big-value slots.
+// Record (self-contained, so stage 2 needs no other read):
+//   label (2 bits) | offset in block (10) | 0 | byte count (19)   if bytes < 2^19
+//   label (2 bits) | offset in block (10) | 1 | part k (2) | bits 17k..17k+16
+//                                              of the byte count  otherwise,
+// one record per 17-bit part up to the highest nonzero one (2 to 4 records);
+// part 0 carries the session's count.  0xFFFFFFFF is the null record (a part 3
+// holds at most bit 51, so no real record has that value).
 // ---------------------------------------------------------------------------
 // Minimum over the 64 lanes of a wave by DPP row shifts and row broadcasts
 // (lanes a row shift or a masked row leaves without a source keep ~0, the
@@ -699,12 +705,18 @@ struct Stage1Shared {
     uint32_t base[kWin];
     uint32_t far[kChunk / 32];
     uint32_t wmin[kStage1Block / 64];
-    uint32_t nbig, nfar;
+    uint32_t nextra, nfar;
 };
 // Static LDS of a stage-1 workgroup: two alternating Stage1Shared and the
 // record buffer (one suffices: a chunk fills it only after its first barrier,
 // which every lane reaches after copying the previous chunk out).
-constexpr size_t kStage1StaticLds = 2 * sizeof(Stage1Shared) + sizeof(uint4) * (kChunk / 4);
+constexpr size_t kStage1StaticLds = 2 * sizeof(Stage1Shared) + sizeof(uint4) * (kChunkSlots / 4);
+
+// Records of one session's byte count (see the record format above).
+__device__ __forceinline__ uint32_t record_parts(unsigned long long by) {
+    if (by < kSmallMax) return 1u;
+    return by < (1ull << 34) ? 2u : (by < (1ull << 51) ? 3u : 4u);
+}
 
 // Stage 1 on one chunk.  c is the chunk within the stream (sessions
 // c * kChunk + ...), g its index in the workspace (slots, directory, far
@@ -760,25 +772,25 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
     if (tid < kWin) sh.cnt[tid] = 0;
     for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block) sh.far[k] = 0;
     if (tid == 0) {
-        sh.nbig = 0;
+        sh.nextra = 0;
         sh.nfar = 0;
     }
     __syncthreads();
     uint32_t bmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int k = 0; k < kStage1Block / 64; ++k) bmin = min(bmin, sh.wmin[k]);
-    uint32_t rank[4], bigi[4];
+    uint32_t rank[4], nrec[4];
     bool loc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t r = blk[k] - bmin;
         loc[k] = inw[k] && r < kWin && by[k] < (1ull << 52);
-        bigi[k] = 0xFFFFFFFFu;
-        if (loc[k] && by[k] >= kSmallMax) {
-            bigi[k] = atomicAdd(&sh.nbig, 1u);
-            if (bigi[k] >= kBigSlots) loc[k] = false;
+        nrec[k] = record_parts(by[k]);
+        if (loc[k] && nrec[k] > 1u) {
+            const uint32_t e = atomicAdd(&sh.nextra, nrec[k] - 1u);
+            if (e + nrec[k] - 1u > (uint32_t)kExtraRecs) loc[k] = false;
         }
-        rank[k] = loc[k] ? atomicAdd(&sh.cnt[r], 1u) : 0u;
+        rank[k] = loc[k] ? atomicAdd(&sh.cnt[r], nrec[k]) : 0u;
         if (inw[k] && !loc[k]) {
             const uint32_t sidx = tid * 4 + k;
             atomicOr(&sh.far[sidx >> 5], 1u << (sidx & 31));
@@ -786,21 +798,24 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
         }
     }
     __syncthreads();
-    if (tid < 64) {  // exclusive scan of the kWin (= 64) block counts, one wave
-        const uint32_t x = sh.cnt[tid];
+    if (tid < 64) {  // exclusive scan of the kWin (= 64) padded block counts, one wave
+        const uint32_t x = (sh.cnt[tid] + 3u) & ~3u;
         uint32_t inc = x;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = (uint32_t)__shfl_up((int)inc, o);
             if ((int)tid >= o) inc += y;
         }
         sh.base[tid] = inc - x;
+        // null records in the padding of the block's segment
+        uint32_t* lpad = reinterpret_cast<uint32_t*>(srec);
+        for (uint32_t q = inc - x + sh.cnt[tid]; q < inc; ++q) lpad[q] = 0xFFFFFFFFu;
         // directory entry of every touched block
         const bool nz = x != 0;
         const unsigned long long m = __ballot(nz);
         const uint32_t e = __popcll(m & ((1ull << tid) - 1ull));
         if (nz) {
             const uint32_t b = b0 + bmin + tid;
-            w.dir[g * kWin + e] = make_uint4(b, (uint32_t)(g * kChunk) + (inc - x), x, 0u);
+            w.dir[g * kWin + e] = make_uint4(b, (uint32_t)(g * kChunkSlots) + (inc - x), x, 0u);
             atomicAdd(w.seg_count + b, 1u);
         }
         if (tid == 0) w.nd[g] = (uint32_t)__popcll(m);
@@ -812,20 +827,20 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
         if (!loc[k]) continue;
         const uint32_t r = blk[k] - bmin;
         const uint32_t off = bin[k] - blk[k] * kBlockBins;
-        uint32_t rec = (lab[k] << 30) | (off << 20);
-        if (bigi[k] != 0xFFFFFFFFu) {
-            rec |= (1u << 19) | bigi[k];
-            w.big[g * kBigSlots + bigi[k]] = by[k];
+        const uint32_t key = (lab[k] << 30) | (off << 20);
+        const uint32_t at = sh.base[r] + rank[k];
+        if (nrec[k] == 1u) {
+            lrec[at] = key | (uint32_t)by[k];
         } else {
-            rec |= (uint32_t)by[k];
+            for (uint32_t q = 0; q < nrec[k]; ++q)
+                lrec[at + q] = key | (1u << 19) | (q << 17) | (uint32_t)((by[k] >> (17 * q)) & 0x1FFFFu);
         }
-        lrec[sh.base[r] + rank[k]] = rec;
     }
     __syncthreads();
     {   // the filled slots of the chunk, one 16-byte store per lane
-        const uint32_t nloc = sh.base[kWin - 1] + sh.cnt[kWin - 1];
-        uint4* dst = reinterpret_cast<uint4*>(w.rec + g * kChunk);
-        for (uint32_t k = tid; k < (nloc + 3) / 4; k += kStage1Block) dst[k] = srec[k];
+        const uint32_t nloc = sh.base[kWin - 1] + ((sh.cnt[kWin - 1] + 3u) & ~3u);
+        uint4* dst = reinterpret_cast<uint4*>(w.rec + g * kChunkSlots);
+        for (uint32_t k = tid; k < nloc / 4; k += kStage1Block) dst[k] = srec[k];
     }
     if (sh.nfar) {
         for (uint32_t k = tid; k < kChunk / 32; k += kStage1Block)
@@ -838,7 +853,7 @@ template <uint32_t KIND>
 __global__ void __launch_bounds__(kStage1Block, 4) k_stage1(PassParams p, PartWs w) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ Stage1Shared sh[2];
-    __shared__ uint4 srec[kChunk / 4];
+    __shared__ uint4 srec[kChunkSlots / 4];
     uint32_t used = 0;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
     Dropped d{};
@@ -940,129 +955,220 @@ __global__ void k_fill(PartWs w) {
     }
 }
 
-// One workgroup per block of kBlockBins bins (all four labels).  The block's
-// segments are taken kSegBatch at a time: their (first slot, count) pairs and
-// a prefix sum of the counts go to LDS, and every lane then walks the batch's
-// records by flat index, so all record loads of a batch are in flight at once.
+// Stage 2.  Persistent workgroups take blocks g = blockIdx.x, + gridDim.x, ...
+// A block's segment descriptors (first slot, 16-byte groups) sit in LDS,
+// double-buffered: while a block's records are accumulated, the next block's
+// descriptors and the segment range of the one after it are in flight.
+// Each wave walks its segments (w, w + 8, ...) as one stream of 16-byte groups,
+// kRecUnroll loads in flight per lane across segment ends.  The accumulators
+// are cleared once and then by the write-out that reads them.
 struct Stage2Shared {
     unsigned long long b[4 * kBlockBins];
     uint32_t c[4 * kBlockBins];
-    uint32_t start[kSegBatch];
-    uint32_t pref[kSegBatch + 1];
-    uint32_t w[kStage2Block / 64];
+    uint32_t start[2][kSegMax];  // first slot (a multiple of 4)
+    uint32_t nvec[2][kSegMax];   // 16-byte groups
+    uint32_t nseg[2];            // described segments
+    uint32_t s0[2], s1[2];       // the block's whole segment range
 };
 
-// gblk: the block's index in the workspace; blk: its index in the stream.
-__device__ __forceinline__ void stage2_block(const PartWs& w, Stage2Shared& sh, uint32_t gblk,
-                                             uint32_t blk, unsigned long long* count,
-                                             unsigned long long* hbytes, uint32_t n_bins,
-                                             int accumulate) {
-    unsigned long long* s_b = sh.b;
-    uint32_t* s_c = sh.c;
-    uint32_t* s_start = sh.start;
-    uint32_t* s_pref = sh.pref;
-    uint32_t* s_w = sh.w;
-    for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
-        s_b[k] = 0;
-        s_c[k] = 0;
+// Where a block's bins go.
+struct BlockOut {
+    unsigned long long* count;
+    unsigned long long* hbytes;
+    uint32_t n_bins;
+    uint32_t blk;  // the block's index in its stream
+    int accumulate;
+};
+
+__device__ __forceinline__ void add_record(Stage2Shared& sh, uint32_t r) {
+    if (r == 0xFFFFFFFFu) return;  // padding
+    const uint32_t key = r >> 20;  // label * kBlockBins + offset
+    if (!((r >> 19) & 1u)) {
+        atomicAdd(&sh.c[key], 1u);
+        atomicAdd(&sh.b[key], (unsigned long long)(r & 0x7FFFFu));
+    } else {
+        const uint32_t q = (r >> 17) & 3u;
+        if (q == 0) atomicAdd(&sh.c[key], 1u);
+        atomicAdd(&sh.b[key], (unsigned long long)(r & 0x1FFFFu) << (17 * q));
     }
-    const uint32_t s0 = w.seg_off[gblk], s1 = w.seg_off[gblk + 1];
-    // Segments are taken kSegBatch at a time; each wave walks whole segments
-    // (contiguous records, so a wave's loads are coalesced) with kRecUnroll
-    // independent loads in flight per lane.
+}
+
+// Accumulate the segments described in buffer d.
+__device__ __forceinline__ void stage2_segments(const PartWs& w, Stage2Shared& sh, uint32_t d) {
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     constexpr uint32_t kWaves = kStage2Block / 64;
-    for (uint32_t sb = s0; sb < s1; sb += kSegBatch) {
-        const uint32_t nseg = min((uint32_t)kSegBatch, s1 - sb);
-        if (threadIdx.x < nseg) {
-            const uint2 sg = w.segs[sb + threadIdx.x];
-            s_start[threadIdx.x] = sg.x;
-            s_pref[threadIdx.x] = sg.y;  // count
-        }
-        __syncthreads();
-        for (uint32_t j = wave; j < nseg; j += kWaves) {
-            const uint32_t start = s_start[j], cnt = s_pref[j];
-            const uint64_t chunk = start / kChunk;
-            auto add = [&](uint32_t r) {
-                const uint32_t key = r >> 20;  // label * kBlockBins + offset
-                const unsigned long long v =
-                    (r >> 19) & 1u ? w.big[chunk * kBigSlots + (r & 0x7FFFFu)]
-                                   : (unsigned long long)(r & 0x7FFFFu);
-                atomicAdd(&s_c[key], 1u);
-                atomicAdd(&s_b[key], v);
-            };
-            // unaligned head and tail one record per lane, the 16-byte aligned
-            // body four records per load, kRecUnroll loads in flight per lane
-            const uint32_t a0 = min((start + 3u) & ~3u, start + cnt);
-            const uint32_t a1 = max(a0, (start + cnt) & ~3u);
-            if (lane < a0 - start) add(w.rec[(uint64_t)start + lane]);
-            if (lane < start + cnt - a1) add(w.rec[(uint64_t)a1 + lane]);
-            const uint4* body = reinterpret_cast<const uint4*>(w.rec + a0);
-            const uint32_t nv = (a1 - a0) / 4;
-            for (uint32_t v0 = 0; v0 < nv; v0 += 64 * kRecUnroll) {
-                uint4 r4[kRecUnroll];
+    const uint32_t nseg = sh.nseg[d];
+    uint32_t j = wave, o = 0;  // the wave's cursor: segment, group offset (wave-uniform)
+    while (j < nseg) {
+        uint4 r4[kRecUnroll];
 #pragma unroll
-                for (int u = 0; u < kRecUnroll; ++u) {
-                    const uint32_t vi = v0 + u * 64 + lane;
-                    r4[u] = vi < nv ? body[vi] : make_uint4(0xFFFFFFFFu, 0, 0, 0);
-                }
-#pragma unroll
-                for (int u = 0; u < kRecUnroll; ++u) {
-                    if (v0 + u * 64 + lane >= nv) continue;
-                    add(r4[u].x);
-                    add(r4[u].y);
-                    add(r4[u].z);
-                    add(r4[u].w);
+        for (int u = 0; u < kRecUnroll; ++u) {
+            r4[u] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+            if (j < nseg) {
+                const uint32_t nv = sh.nvec[d][j];
+                if (o + lane < nv)
+                    r4[u] = reinterpret_cast<const uint4*>(w.rec + sh.start[d][j])[o + lane];
+                o += 64;
+                if (o >= nv) {
+                    o = 0;
+                    j += kWaves;
                 }
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kRecUnroll; ++u) {
+            add_record(sh, r4[u].x);
+            add_record(sh, r4[u].y);
+            add_record(sh, r4[u].z);
+            add_record(sh, r4[u].w);
+        }
     }
-    __syncthreads();
-    // write the block: two consecutive bins per lane (16-byte stores when the
-    // label row is 16-byte aligned, which holds when n_bins is even)
-    const uint64_t b0 = (uint64_t)blk * kBlockBins;
-    const bool pairs = (n_bins & 1u) == 0 && (((uintptr_t)count | (uintptr_t)hbytes) & 15u) == 0;
+}
+
+// Descriptors of segments [s, s + n) of the current block into buffer d
+// (n <= kSegMax), by the whole workgroup.
+__device__ __forceinline__ void stage2_describe(const PartWs& w, Stage2Shared& sh, uint32_t d,
+                                                uint32_t s, uint32_t n) {
+    for (uint32_t k = threadIdx.x; k < n; k += kStage2Block) {
+        const uint2 sg = w.segs[s + k];
+        sh.start[d][k] = sg.x;
+        sh.nvec[d][k] = sg.y >> 2;
+    }
+    if (threadIdx.x == 0) sh.nseg[d] = n;
+}
+
+// Write the block's bins (two consecutive bins per lane, 16-byte stores when
+// the label rows are 16-byte aligned, which holds when n_bins is even) and
+// clear the accumulators it read.
+__device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t) {
+    const uint64_t b0 = (uint64_t)t.blk * kBlockBins;
+    const bool pairs =
+        (t.n_bins & 1u) == 0 && (((uintptr_t)t.count | (uintptr_t)t.hbytes) & 15u) == 0;
     if (pairs) {
         for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
             const uint32_t e = 2 * k;
             const uint32_t lab = e / kBlockBins, off = e % kBlockBins;
             const uint64_t bin = b0 + off;
-            if (bin >= n_bins) continue;  // n_bins even: bin + 1 is inside too
-            const uint64_t o = (uint64_t)lab * n_bins + bin;
-            ulonglong2 c = make_ulonglong2(s_c[e], s_c[e + 1]);
-            ulonglong2 b = make_ulonglong2(s_b[e], s_b[e + 1]);
-            if (accumulate) {
-                const ulonglong2 oc = *reinterpret_cast<const ulonglong2*>(count + o);
-                const ulonglong2 ob = *reinterpret_cast<const ulonglong2*>(hbytes + o);
-                c.x += oc.x; c.y += oc.y;
-                b.x += ob.x; b.y += ob.y;
+            ulonglong2 c = make_ulonglong2(sh.c[e], sh.c[e + 1]);
+            ulonglong2 b = make_ulonglong2(sh.b[e], sh.b[e + 1]);
+            sh.c[e] = 0;
+            sh.c[e + 1] = 0;
+            sh.b[e] = 0;
+            sh.b[e + 1] = 0;
+            if (bin >= t.n_bins) continue;  // n_bins even: bin + 1 is inside too
+            const uint64_t o = (uint64_t)lab * t.n_bins + bin;
+            if (t.accumulate) {
+                const ulonglong2 oc = *reinterpret_cast<const ulonglong2*>(t.count + o);
+                const ulonglong2 ob = *reinterpret_cast<const ulonglong2*>(t.hbytes + o);
+                c.x += oc.x;
+                c.y += oc.y;
+                b.x += ob.x;
+                b.y += ob.y;
             }
-            *reinterpret_cast<ulonglong2*>(count + o) = c;
-            *reinterpret_cast<ulonglong2*>(hbytes + o) = b;
+            *reinterpret_cast<ulonglong2*>(t.count + o) = c;
+            *reinterpret_cast<ulonglong2*>(t.hbytes + o) = b;
         }
     } else {
         for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
             const uint32_t lab = k / kBlockBins, off = k % kBlockBins;
             const uint64_t bin = b0 + off;
-            if (bin >= n_bins) continue;
-            const uint64_t o = (uint64_t)lab * n_bins + bin;
-            unsigned long long c = s_c[k], b = s_b[k];
-            if (accumulate) {
-                c += count[o];
-                b += hbytes[o];
+            unsigned long long c = sh.c[k], b = sh.b[k];
+            sh.c[k] = 0;
+            sh.b[k] = 0;
+            if (bin >= t.n_bins) continue;
+            const uint64_t o = (uint64_t)lab * t.n_bins + bin;
+            if (t.accumulate) {
+                c += t.count[o];
+                b += t.hbytes[o];
             }
-            count[o] = c;
-            hbytes[o] = b;
+            t.count[o] = c;
+            t.hbytes[o] = b;
         }
     }
 }
+
+// The persistent block loop; out(g) names where block g's bins go.
+template <class Out>
+__device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, const Out& out) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t G = gridDim.x, nb = w.n_blocks;
+    uint32_t g = blockIdx.x;
+    if (g >= nb) return;
+    for (uint32_t k = tid; k < 4 * kBlockBins; k += kStage2Block) {
+        sh.b[k] = 0;
+        sh.c[k] = 0;
+    }
+    {
+        const uint32_t s0 = w.seg_off[g], s1 = w.seg_off[g + 1];
+        stage2_describe(w, sh, 0, s0, min(s1 - s0, (uint32_t)kSegMax));
+        if (tid == 0) {
+            sh.s0[0] = s0;
+            sh.s1[0] = s1;
+        }
+    }
+    uint32_t gn = g + G;  // next block, and its segment range
+    uint32_t n0 = 0, n1 = 0;
+    if (gn < nb) {
+        n0 = w.seg_off[gn];
+        n1 = w.seg_off[gn + 1];
+    }
+    for (uint32_t d = 0; g < nb; g = gn, gn += G, d ^= 1u) {
+        __syncthreads();  // descriptors of g in buffer d, accumulators clear
+        // in flight during this block: the next block's descriptors and the
+        // segment range of the block after it
+        const uint32_t nn = gn < nb ? min(n1 - n0, (uint32_t)kSegMax) : 0u;
+        uint2 nsg = make_uint2(0u, 0u);
+        if (tid < nn) nsg = w.segs[n0 + tid];
+        const uint32_t gnn = gn + G;
+        uint32_t m0 = 0, m1 = 0;
+        if (gnn < nb) {
+            m0 = w.seg_off[gnn];
+            m1 = w.seg_off[gnn + 1];
+        }
+        stage2_segments(w, sh, d);
+        // blocks with more than kSegMax segments (unsorted input): further
+        // batches through the same buffer
+        const uint32_t s0 = sh.s0[d], s1 = sh.s1[d];
+        for (uint32_t sb = s0 + kSegMax; sb < s1; sb += kSegMax) {
+            __syncthreads();
+            stage2_describe(w, sh, d, sb, min(s1 - sb, (uint32_t)kSegMax));
+            __syncthreads();
+            stage2_segments(w, sh, d);
+        }
+        __syncthreads();  // accumulation complete
+        stage2_write(sh, out(g));
+        if (gn < nb) {
+            const uint32_t e = d ^ 1u;  // last read before this block's first barrier
+            if (tid < nn) {
+                sh.start[e][tid] = nsg.x;
+                sh.nvec[e][tid] = nsg.y >> 2;
+            }
+            if (tid == 0) {
+                sh.nseg[e] = nn;
+                sh.s0[e] = n0;
+                sh.s1[e] = n1;
+            }
+        }
+        n0 = m0;
+        n1 = m1;
+    }
+}
+
+struct PlainOut {
+    unsigned long long* count;
+    unsigned long long* hbytes;
+    uint32_t n_bins;
+    int accumulate;
+    __device__ BlockOut operator()(uint32_t g) const {
+        return BlockOut{count, hbytes, n_bins, g, accumulate};
+    }
+};
 
 __global__ void __launch_bounds__(kStage2Block) k_stage2(PartWs w, unsigned long long* count,
                                                         unsigned long long* hbytes, uint32_t n_bins,
                                                         int accumulate) {
     __shared__ Stage2Shared sh;
-    stage2_block(w, sh, blockIdx.x, blockIdx.x, count, hbytes, n_bins, accumulate);
+    stage2_run(w, sh, PlainOut{count, hbytes, n_bins, accumulate});
 }
 
 __global__ void k_zero(unsigned long long* __restrict__ p, uint64_t n) {
@@ -1102,7 +1208,7 @@ template <uint32_t KIND>
 __device__ __forceinline__ void batch_stage1(const BatchArgs& a, const PartWs& w) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ Stage1Shared sh[2];
-    __shared__ uint4 srec[kChunk / 4];
+    __shared__ uint4 srec[kChunkSlots / 4];
     __shared__ uint32_t s_item;
     __shared__ BatchStreamDev s_bs;  // the current stream's descriptor
     const uint32_t tid = threadIdx.x;
@@ -1178,20 +1284,26 @@ __device__ __forceinline__ void batch_stage1(const BatchArgs& a, const PartWs& w
     }
 }
 
+// Block g of the shared workspace belongs to the last stream whose first
+// block is <= g (streams without blocks share their base with the next one).
+struct BatchOut {
+    const BatchArgs* a;
+    __device__ BlockOut operator()(uint32_t gb) const {
+        uint32_t lo = 0, n = a->n_streams;
+        while (n > 1) {
+            const uint32_t half = n >> 1;
+            lo = a->block_base[lo + half] <= gb ? lo + half : lo;
+            n -= half;
+        }
+        while (lo + 1 < a->n_streams && a->block_base[lo + 1] <= gb) ++lo;
+        const BatchStreamDev& bs = a->streams[lo];
+        return BlockOut{bs.p.count, bs.p.hbytes, bs.p.n_bins, gb - bs.block0, 0};
+    }
+};
+
 __global__ void __launch_bounds__(kStage2Block) k_batch_stage2(BatchArgs a, PartWs w) {
     __shared__ Stage2Shared sh;
-    const uint32_t gb = blockIdx.x;
-    // stream owning the block: last s with block_base[s] <= gb
-    uint32_t lo = 0, n = a.n_streams;
-    while (n > 1) {
-        const uint32_t half = n >> 1;
-        lo = a.block_base[lo + half] <= gb ? lo + half : lo;
-        n -= half;
-    }
-    // skip streams without blocks (equal bases)
-    while (lo + 1 < a.n_streams && a.block_base[lo + 1] <= gb) ++lo;
-    const BatchStreamDev& bs = a.streams[lo];
-    stage2_block(w, sh, gb, gb - bs.block0, bs.p.count, bs.p.hbytes, bs.p.n_bins, 0);
+    stage2_run(w, sh, BatchOut{&a});
 }
 
 
@@ -1395,11 +1507,18 @@ static sinet_status launch_zero32(uint32_t* p, uint64_t n, hipStream_t s) {
 // ---- workspace of the partitioned histogram --------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Persistent stage-2 workgroups: as many as fit on the device at once.
+static uint32_t stage2_grid(uint32_t n_blocks) {
+    static const uint32_t per_cu = (uint32_t)blocks_per_cu((const void*)k_stage2, kStage2Block, 0);
+    const uint64_t g = (uint64_t)device_cu_count() * (per_cu ? per_cu : 1u);
+    return (uint32_t)(g < n_blocks ? g : n_blocks);
+}
+
 size_t part_ws_bytes(uint64_t n, uint32_t n_bins) {
     const uint64_t nc = (n + kChunk - 1) / kChunk;
     const uint64_t nb = (n_bins + kBlockBins - 1) / kBlockBins;
     const uint64_t nt = (nb + 1 + 1023) / 1024;
-    return al256(4 * nc * kChunk) + al256(8 * nc * kBigSlots) + al256(16 * nc * kWin) +
+    return al256(4 * nc * kChunkSlots) + al256(16 * nc * kWin) +
            al256(4 * nc) + al256(4 * nc * (kChunk / 32)) + al256(4 * (nc + 1)) + al256(4 * nb) +
            al256(4 * (nb + 1)) + al256(8 * nc * kWin) + al256(4 * nt) + 256;
 }
@@ -1412,8 +1531,7 @@ PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins) {
     char* a = (char*)base;
     size_t o = 0;
     auto take = [&](size_t bytes) { char* r = a + o; o += al256(bytes); return (void*)r; };
-    w.rec = (uint32_t*)take(4 * nc * kChunk);
-    w.big = (unsigned long long*)take(8 * nc * kBigSlots);
+    w.rec = (uint32_t*)take(4 * nc * kChunkSlots);
     w.dir = (uint4*)take(16 * nc * kWin);
     w.nd = (uint32_t*)take(4 * nc);
     w.farbits = (uint32_t*)take(4 * nc * (kChunk / 32));
@@ -1563,7 +1681,8 @@ sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& 
     if (st != SINET_OK) return st;
     {
         PhaseScope ph(PH_STAGE2, s);
-        hipLaunchKernelGGL(k_stage2, dim3(nb), dim3(kStage2Block), 0, s, wv, p.count, p.hbytes,
+        const uint32_t g2 = stage2_grid(nb);
+        hipLaunchKernelGGL(k_stage2, dim3(g2), dim3(kStage2Block), 0, s, wv, p.count, p.hbytes,
                            p.n_bins, accumulate);
         st = check_hip(hipGetLastError(), "stage-2 launch");
     }
@@ -1625,7 +1744,7 @@ sinet_status launch_batch_stage1(uint32_t kind, const BatchArgs& a, const PartWs
 sinet_status launch_batch_stage2(const BatchArgs& a, const PartWs& w, uint32_t n_blocks,
                                  hipStream_t s) {
     if (n_blocks == 0) return SINET_OK;
-    hipLaunchKernelGGL(k_batch_stage2, dim3(n_blocks), dim3(kStage2Block), 0, s, a, w);
+    hipLaunchKernelGGL(k_batch_stage2, dim3(stage2_grid(n_blocks)), dim3(kStage2Block), 0, s, a, w);
     return check_hip(hipGetLastError(), "batch stage-2 launch");
 }
 

@@ -71,21 +71,23 @@ __host__ __device__ constexpr uint32_t radix_words(uint32_t bits) {
 constexpr int kChunk = 2048;        // sessions per stage-1 chunk
 constexpr int kBlockBins = 1024;    // bins per stage-2 block (all four labels)
 constexpr int kWin = 64;            // blocks one chunk may touch without the far path
-constexpr int kBigSlots = 128;      // 64-bit byte counts a chunk can hold out of line
+constexpr int kExtraRecs = 384;     // records beyond one per session a chunk may hold
+// record slots of a chunk: one per session, the extra part records of large byte
+// counts, and the padding of every block's segment to whole 16-byte groups
+constexpr int kChunkSlots = kChunk + kExtraRecs + 3 * kWin;
 constexpr int kStage1Block = kChunk / 4;  // stage-1 lanes: 4 sessions each
 
 // Device workspace of the partitioned histogram (carved from one allocation).
 struct PartWs {
-    uint32_t* rec;                  // [n_chunks * kChunk] 4-byte records
-    unsigned long long* big;        // [n_chunks * kBigSlots] out-of-line byte counts
-    uint4* dir;                     // [n_chunks * kWin] (block, first slot, count, -)
+    uint32_t* rec;                  // [n_chunks * kChunkSlots] 4-byte records
+    uint4* dir;                     // [n_chunks * kWin] (block, first slot, slots, -)
     uint32_t* nd;                   // [n_chunks] directory entries per chunk
     uint32_t* farbits;              // [n_chunks * kChunk / 32] far sessions (flagged chunks)
     uint32_t* farlist;              // [n_chunks] chunks holding far sessions
     uint32_t* farcount;             // [1]
     uint32_t* seg_count;            // [n_blocks] directory entries per block
     uint32_t* seg_off;              // [n_blocks + 1] exclusive scan of seg_count
-    uint2* segs;                    // [n_chunks * kWin] (first slot, count) grouped by block
+    uint2* segs;                    // [n_chunks * kWin] (first slot, slots) grouped by block
     uint32_t* scan_tiles;           // scan scratch
     uint64_t n_chunks;
     uint32_t n_blocks;

@@ -298,6 +298,31 @@ def test_inout_index_dense_blocks(sinet, torch):
         assert np.array_equal(lab.cpu().numpy(), elab)
 
 
+@pytest.mark.parametrize("kind", ["bsearch", "trie"])
+def test_byte_magnitudes_and_record_overflow(sinet, torch, kind):
+    """Byte counts of every magnitude (one to four 17-bit part records, and
+    the far path from 2^52 on), sorted and shuffled time order, and chunks
+    whose large counts exceed the extra record slots."""
+    wl = sinetgen.config(1)
+    rng = np.random.default_rng(21)
+    n = 3 * 2048 * 7 + 123
+    k = rng.integers(0, 64, n)
+    by = (np.uint64(1) << k.astype(np.uint64)) + rng.integers(0, 1 << 16, n).astype(np.uint64)
+    by[: 2048 * 3] = (np.uint64(1) << np.uint64(40)) + rng.integers(0, 1 << 30, 2048 * 3).astype(np.uint64)
+    ts = np.sort(rng.integers(0, 3_000_000, n)).astype(np.uint32)
+    s = sinetgen.sessions(wl, start=0, stop=n)
+    for order in ("sorted", "shuffled"):
+        t = ts if order == "sorted" else rng.permutation(ts)
+        T, S, D, B = _up(sinet, {"ts": t, "src": s["src"], "dst": s["dst"], "bytes": by})
+        tab = sinet.Table(wl.pbase, wl.plen, kind=kind)
+        lab, out = sinet.pipeline(tab, T, S, D, B, 0, 1, 3_000_000)
+        torch.cuda.synchronize()
+        elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, t, s["src"], s["dst"], by, 0, 1,
+                                           3_000_000)
+        assert np.array_equal(lab.cpu().numpy(), elab), order
+        _cmp_hist(sinet, out, (ec, eb, ed))
+
+
 def test_empty_input_clears_or_keeps(sinet, torch):
     b, l = _edge_table()
     tab = sinet.Table(b, l, kind="bsearch")
