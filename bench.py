@@ -40,8 +40,16 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SESSION = 21   # ts 4 + src 4 + dst 4 + bytes 8 read, label 1 written
 BYTES_PER_BIN = 64       # 4 labels x (count 8 + bytes 8) written once
 DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched"
-# HBM bytes per launch from the counter runs (see measured_traffic)
-COUNTER_TRAFFIC = {}
+# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of the
+# plain form on the default day, scaled by the counters of a plain copy
+# (read x2.000, write x1.000)
+COUNTER_TRAFFIC = {
+    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "f86265f80aa9a95f",
+                 "bytes": 40.32e9},
+    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "f86265f80aa9a95f",
+                 "bytes": 12.98e9},
+}
+KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")
 
 
 def log(*a):
@@ -92,7 +100,7 @@ def time_calls(torch, fn, steps, warmup, sinet=None):
     return sum(dev) / len(dev), min(dev), wall * 1e3 / steps, phases
 
 
-def kernel_roofline(phases, n, n_bins, steps):
+def kernel_roofline(phases, n, n_bins, steps, workload):
     """Roofline of the dominant kernel of the step from the library's phase
     events over the timed calls: the stage-1 kernel (read ts/src/dst/bytes,
     20 B, and write the label, 1 B, per session) or the stage-2 kernel (write
@@ -100,34 +108,39 @@ def kernel_roofline(phases, n, n_bins, steps):
     if phases is None or phases["stage1_launches"] == 0:
         return None
     launches = phases["stage1_launches"]
+    per_step = launches / steps          # launches of each kernel in one step
     cand = []
     # the fused stage 1 carries the whole per-session traffic; after a
     # separate lookup pass it reads ts, bytes and the stored label (13 B)
     fused = phases["lookup_ms"] == 0.0
     cand.append(("k_stage1", phases["stage1_ms"] / launches,
-                 (BYTES_PER_SESSION if fused else 13) * n / launches))
+                 (BYTES_PER_SESSION if fused else 13) * n / per_step))
     if phases["stage2_ms"] > 0:
-        cand.append(("k_stage2", phases["stage2_ms"] / launches, BYTES_PER_BIN * n_bins / launches))
+        cand.append(("k_stage2", phases["stage2_ms"] / launches, BYTES_PER_BIN * n_bins / per_step))
     if not fused:
-        cand.append(("k_pass (lookup, labels stored)", phases["lookup_ms"] / launches, 9 * n / launches))
+        cand.append(("k_pass (lookup, labels stored)", phases["lookup_ms"] / launches,
+                     9 * n / per_step))
     name, ms, alg = max(cand, key=lambda c: c[1])
     achieved = alg / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(name)
+    traffic = measured_traffic(name, workload)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
             "alg_bytes_per_launch": alg, "launch_ms": ms, "launches": launches, "steps": steps}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of the kernel from the FETCH_SIZE / WRITE_SIZE
     counter runs of the default workload, scaled by the same counters of a
-    plain copy; null when the kernel source has changed since."""
+    plain copy; null for another workload or when the kernel sources have
+    changed since."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2106_12863_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_12863_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()[:16]
     rec = COUNTER_TRAFFIC.get(kernel)
-    if rec is None or rec["kernels_sha"] != sha:
+    if rec is None or rec["kernels_sha"] != sha or rec["workload"] != workload:
         return None
     return rec["bytes"]
 
@@ -227,7 +240,7 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     head = forms[0]
     r = results[head]
     alg_bytes = BYTES_PER_SESSION * wl.n + BYTES_PER_BIN * w.n_bins
-    roof = kernel_roofline(r.get("_phases"), wl.n, w.n_bins, args.steps)
+    roof = kernel_roofline(r.get("_phases"), wl.n, w.n_bins, args.steps, wl.name)
     line = {
         "metric": METRIC, "value": r["sessions_per_s"], "unit": "sessions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -246,7 +259,7 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     for k, v in results.items():
         line["forms"][k]["hbm_frac"] = alg_bytes / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     if not args.no_cpu:
-        sample = args.cpu_sample or (20_000_000 if wl.n_prefix <= 4096 else 8_000_000)
+        sample = args.cpu_sample or (60_000_000 if wl.n_prefix <= 4096 else 30_000_000)
         line["cpu_baseline"] = cpu_baseline(wl, cols, sinet, sample)
     return line
 
