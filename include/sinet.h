@@ -123,6 +123,10 @@ typedef struct {
     uint32_t trained;       /* learned kinds: 1 after sinet_table_train      */
     uint32_t max_err;       /* learned kinds: measured bound of the search   */
     uint32_t segments;      /* PLA: number of segments                       */
+    uint32_t pla_window;    /* PLA: 1 when max_err <= 6, so that each lookup
+                               reads one aligned window of 16 boundaries from
+                               device memory instead of searching an LDS
+                               sample of them                                */
     uint64_t fallbacks;     /* learned kinds: bounded searches that fell back
                                to the full search since create (synchronous
                                read of a device counter)                     */
@@ -190,7 +194,10 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
 
 /* Fit the learned model of a LEARNED_PLA / LEARNED_MLP table on the GPU and
  * measure its maximum position error over every interval.  params may be
- * NULL (defaults); report may be NULL.  Synchronous. */
+ * NULL (defaults); report may be NULL.  PLA with segments == 0: error-bounded
+ * segmentation on the host; with target_err == 0 it first aims at a measured
+ * bound of at most 6 (the window search, see pla_window) if those segments
+ * fit in LDS, else at 8, doubled until the segments fit.  Synchronous. */
 sinet_status sinet_table_train(sinet_table* t, const sinet_train_params* params,
                                hipStream_t stream, sinet_train_report* report);
 

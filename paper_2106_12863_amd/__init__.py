@@ -50,7 +50,8 @@ class Hist(ctypes.Structure):
 class TableInfo(ctypes.Structure):
     _fields_ = [("kind", U32), ("inout_index", U32), ("n_prefix", U64), ("m", U64),
                 ("device_bytes", U64),
-                ("trained", U32), ("max_err", U32), ("segments", U32), ("fallbacks", U64)]
+                ("trained", U32), ("max_err", U32), ("segments", U32), ("pla_window", U32),
+                ("fallbacks", U64)]
 
 
 class TrainParams(ctypes.Structure):

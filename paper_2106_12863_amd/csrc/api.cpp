@@ -138,16 +138,19 @@ static uint32_t lds_bytes_for(const DevTable& t, uint32_t kind) {
         case SINET_LOOKUP_SCAN: return 12u * t.n_prefix;
         case SINET_LOOKUP_BSEARCH: words = t.n_top; break;
         case SINET_LOOKUP_TRIE: break;
-        case SINET_LOOKUP_LEARNED_PLA: words = t.n_top + 3 * t.segments + radix_words(t.radix_bits); break;
+        case SINET_LOOKUP_LEARNED_PLA:
+            words = (t.pla_window ? 0u : t.n_top) + 3 * t.segments + radix_words(t.radix_bits);
+            break;
         case SINET_LOOKUP_LEARNED_MLP: words = t.n_top + SINET_MLP_PARAMS; break;
         default: break;
     }
     return 4u * (words + t.lds_member_words + (t.filter_lds ? kFilterWords : 0u));
 }
 
-// LDS words a PLA of S segments needs next to the filter and member bits.
-static uint32_t pla_lds_words(const DevTable& t, uint32_t S) {
-    return t.n_top + 3 * S + radix_words(t.radix_bits) + t.lds_member_words +
+// LDS words a PLA of S segments needs next to the filter and member bits;
+// the window search needs no sample of the boundaries.
+static uint32_t pla_lds_words(const DevTable& t, uint32_t S, bool window) {
+    return (window ? 0u : t.n_top) + 3 * S + radix_words(t.radix_bits) + t.lds_member_words +
            (t.filter_lds ? kFilterWords : 0u);
 }
 
@@ -289,7 +292,7 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     // boundaries padded with 0xFFFFFFFF to whole leaf blocks of 2^top_log2
     const uint64_t m_pad = (uint64_t)n_top << top_log2;
     std::vector<uint32_t> Bpad(t->B);
-    Bpad.resize(m_pad, 0xFFFFFFFFu);
+    Bpad.resize(m_pad + kBTail, 0xFFFFFFFFu);
     std::vector<uint32_t> filter;
     if (interval_kind) build_filter(t->B, t->owner, filter);
     std::vector<uint32_t> io;
@@ -307,7 +310,7 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     const uint32_t rw = learned ? radix_words(kPlaRadixBits) : 0;
-    const size_t oB = take(4ull * m_pad), oOwn = take(4ull * m), oMem = take(4ull * mw),
+    const size_t oB = take(4ull * (m_pad + kBTail)), oOwn = take(4ull * m), oMem = take(4ull * mw),
                  oInst = take(4 * P), oCb = take(4 * P), oMk = take(4 * P), oLn = take(4 * P),
                  oTop = take(4ull * n_top), oTrie = take(4 * trie.size()),
                  oKnot = take(4ull * smax), oC = take(4ull * smax), oG = take(4ull * smax),
@@ -327,7 +330,7 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
         return hipMemcpyAsync(a + o, src, bytes, hipMemcpyHostToDevice, stream);
     };
     hipError_t r = hipSuccess;
-    if (r == hipSuccess) r = up(oB, Bpad.data(), 4ull * m_pad);
+    if (r == hipSuccess) r = up(oB, Bpad.data(), 4ull * (m_pad + kBTail));
     if (r == hipSuccess) r = up(oFilter, filter.data(), 4ull * filter.size());
     if (r == hipSuccess) r = up(oIo, io.data(), 4ull * io.size());
     if (r == hipSuccess) r = up(oOwn, t->owner.data(), 4ull * m);
@@ -396,10 +399,17 @@ sinet_status sinet_table_train(sinet_table* t, const sinet_train_params* params,
         const uint32_t S = params ? params->segments : 0;
         const uint32_t E = params ? params->target_err : 0;
         if (S > kMaxSegments) return fail(SINET_ERR_INVALID_ARG, "segments above 65535");
-        if (S && pla_lds_words(t->dev, S) + kLdsReserveWords > t->lds_words)
+        if (S && pla_lds_words(t->dev, S, false) + kLdsReserveWords > t->lds_words)
             return fail(SINET_ERR_INVALID_ARG, "segments do not fit in LDS next to the filter and member bits");
-        const uint32_t smax = (t->lds_words - kLdsReserveWords - pla_lds_words(t->dev, 0)) / 3;
-        st = train_pla(t, S, E, std::min(smax, kMaxSegments), stream, &rep);
+        const uint32_t budget = t->lds_words - kLdsReserveWords;
+        auto room = [&](bool window) {
+            const uint32_t used = pla_lds_words(t->dev, 0, window);
+            return used < budget ? (budget - used) / 3 : 0u;
+        };
+        const uint32_t smax = room(false), smax_window = room(true);
+        if (smax_window == 0) return fail(SINET_ERR_UNSUPPORTED, "no LDS left for PLA segments");
+        st = train_pla(t, S, E, std::min(smax, kMaxSegments), std::min(smax_window, kMaxSegments),
+                       stream, &rep);
     } else if (t->kind == SINET_LOOKUP_LEARNED_MLP) {
         st = train_mlp(t, params, stream, &rep);
     } else {
@@ -423,6 +433,7 @@ sinet_status sinet_table_info(const sinet_table* t, sinet_table_info_t* out) {
     out->trained = (uint32_t)t->trained;
     out->max_err = t->dev.max_err;
     out->segments = t->dev.segments;
+    out->pla_window = t->dev.pla_window;
     unsigned long long fb = 0;
     hipError_t e = hipMemcpy(&fb, t->dev.fallbacks, 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return check_hip(e, "fallback counter read");
@@ -463,7 +474,7 @@ sinet_status sinet_table_set_model(sinet_table* t, const float* params, const ui
         if (!knot || !c || !g) return fail(SINET_ERR_INVALID_ARG, "PLA arrays are NULL");
         if (segments == 0 || segments > kMaxSegments || segments > t->dev.m)
             return fail(SINET_ERR_INVALID_ARG, "bad segment count");
-        if (pla_lds_words(t->dev, segments) + kLdsReserveWords > t->lds_words)
+        if (pla_lds_words(t->dev, segments, true) + kLdsReserveWords > t->lds_words)
             return fail(SINET_ERR_INVALID_ARG, "segments do not fit in LDS next to the filter and member bits");
         if (knot[0] != 0) return fail(SINET_ERR_INVALID_ARG, "knot[0] must be 0");
         for (uint32_t s = 0; s < segments; ++s) {
@@ -486,6 +497,18 @@ sinet_status sinet_table_set_model(sinet_table* t, const float* params, const ui
         if (st != SINET_OK) return st;
     }
     t->dev.max_err = max_err;
+    // the window search needs a bound of at most kPlaWindowErr; otherwise the
+    // LDS sample of the boundaries must fit next to the segments
+    t->dev.pla_window = 0;
+    if (t->kind == SINET_LOOKUP_LEARNED_PLA) {
+        if (max_err <= kPlaWindowErr) {
+            t->dev.pla_window = 1;
+        } else if (pla_lds_words(t->dev, segments, false) + kLdsReserveWords > t->lds_words) {
+            t->trained = 0;
+            return fail(SINET_ERR_INVALID_ARG,
+                        "bound above 6 and the segments leave no LDS for the boundary sample");
+        }
+    }
     t->trained = 1;
     t->dev.lds_bytes = lds_bytes_for(t->dev, t->kind);
     return SINET_OK;

@@ -181,6 +181,55 @@ __device__ __forceinline__ void learned_search_n(const DevTable& t, const LdsVie
     leaf_search<N>(t, a, j, need);
 }
 
+// PLA window search (max_err = e <= kPlaWindowErr): the interval of a lies
+// within e of the rounded prediction p, so the 16 boundaries from
+// s = (p - e) rounded down to a multiple of 4 hold it.  They are read with
+// four aligned 16-byte loads (two addresses' windows in flight at once), and
+// j = s + (the number of them <= a) - 1.  A count of 0, or of 16 with
+// B[s + 16] <= a, means the bound was wrong: the full search answers, counted.
+template <int N>
+__device__ __forceinline__ void window_search_n(const DevTable& t, const uint32_t* a, const int* p,
+                                                uint32_t* j, uint32_t need) {
+    constexpr int G = N < 2 ? N : 2;
+    const int e = (int)t.max_err;
+#pragma unroll
+    for (int q0 = 0; q0 < N; q0 += G) {
+        uint4 w[G][4];
+        uint32_t s[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            s[q] = (uint32_t)max(p[q0 + q] - e, 0) & ~3u;
+            if ((need >> (q0 + q)) & 1u) {
+                const uint4* b4 = reinterpret_cast<const uint4*>(t.B + s[q]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w[q][v] = b4[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w[q][v] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int qq = q0 + q;
+            if (!((need >> qq) & 1u)) continue;
+            const uint32_t x = a[qq];
+            uint32_t c = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                c += (uint32_t)(w[q][v].x <= x) + (uint32_t)(w[q][v].y <= x) +
+                     (uint32_t)(w[q][v].z <= x) + (uint32_t)(w[q][v].w <= x);
+            bool ok = c >= 1u;
+            if (c == 16u && s[q] + 16u < t.m) ok = x < t.B[s[q] + 16u];
+            uint32_t r = s[q] + c - 1u;
+            if (!ok) {
+                atomicAdd(t.fallbacks, 1ull);
+                r = upper_last(t.B, t.m, x);
+            }
+            j[qq] = min(r, t.m - 1);
+        }
+    }
+}
+
 // Interval index of each address (all kinds but SCAN).  Addresses whose bit
 // in `need` is clear are skipped (their j is left unspecified); skipped lanes
 // issue no memory requests.
@@ -214,7 +263,8 @@ __device__ __forceinline__ void intervals(const DevTable& t, const LdsView& v, c
             const uint32_t s = s0 + upper_last(v.knot + s0, s1 - s0 + 1, a[q]);
             p[q] = clamp_pos(pla_eval(v.knot[s], v.c[s], v.g[s], a[q]), t.m);
         }
-        learned_search_n<N>(t, v, a, p, j, need);
+        if (t.pla_window) window_search_n<N>(t, a, p, j, need);
+        else learned_search_n<N>(t, v, a, p, j, need);
     } else {  // KK_MLP
         int p[N];
 #pragma unroll
@@ -504,8 +554,8 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) 
         v.len = copy(t.len, t.n_prefix);
     } else if constexpr (KIND != KK_LABEL_IN) {
         v.filter = t.filter_lds ? copy(t.filter, kFilterWords) : t.filter;
-        if constexpr (KIND == KK_BSEARCH || KIND == KK_PLA || KIND == KK_MLP)
-            v.top = copy(t.top, t.n_top);
+        if constexpr (KIND == KK_BSEARCH || KIND == KK_MLP) v.top = copy(t.top, t.n_top);
+        if constexpr (KIND == KK_PLA) v.top = t.pla_window ? nullptr : copy(t.top, t.n_top);
         if constexpr (KIND == KK_PLA) {
             v.knot = copy(t.knot, t.segments);
             v.c = reinterpret_cast<const float*>(

@@ -195,54 +195,90 @@ static void cone_segments(const std::vector<uint32_t>& B, double E, std::vector<
     }
 }
 
-sinet_status train_pla(sinet_table* t, uint32_t S, uint32_t E, uint32_t max_segments, hipStream_t s,
-                       sinet_train_report* r) {
+// Upload a segmentation, its radix directory, and measure its bound.
+static sinet_status set_segments(sinet_table* t, const std::vector<uint32_t>& knots,
+                                 const std::vector<float>& c, const std::vector<float>& g,
+                                 hipStream_t s, uint32_t* err) {
+    DevTable& d = t->dev;
+    const uint32_t S = (uint32_t)knots.size();
+    hipError_t e = hipMemcpyAsync((void*)d.knot, knots.data(), 4ull * S, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)d.pla_c, c.data(), 4ull * S, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)d.pla_g, g.data(), 4ull * S, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return check_hip(e, "PLA upload");
+    d.segments = S;
+    e = upload_radix(t, knots);
+    if (e != hipSuccess) return check_hip(e, "PLA directory upload");
+    return measure_err(d, false, s, err);
+}
+
+// S > 0: S equal-count segments fitted on the GPU.  S == 0: error-bounded
+// segmentation for target E; E == 0 first tries bounds that allow the window
+// search (measured max_err <= kPlaWindowErr) with at most max_window
+// segments, then 8, doubled until the segments fit max_segments.
+sinet_status train_pla(sinet_table* t, uint32_t S, uint32_t E, uint32_t max_segments,
+                       uint32_t max_window, hipStream_t s, sinet_train_report* r) {
     DevTable& d = t->dev;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventRecord(e0, s);
     std::vector<uint32_t> knots;
-    hipError_t e = hipSuccess;
+    uint32_t err = 0;
+    bool window = false;
     if (S) {
         // equal-count segments, least-squares lines fitted on the GPU
         if (S > d.m) S = d.m;
         if (S > max_segments) S = max_segments;
         hipLaunchKernelGGL(k_pla_fit, dim3(S), dim3(256), 0, s, d.B, d.m, S, (uint32_t*)d.knot,
                            (float*)d.pla_c, (float*)d.pla_g);
-        e = hipGetLastError();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return check_hip(e, "PLA fit");
         knots.resize(S);
         for (uint32_t k = 0; k < S; ++k) knots[k] = t->B[(uint64_t)k * d.m / S];
+        d.segments = S;
+        e = upload_radix(t, knots);
+        if (e != hipSuccess) return check_hip(e, "PLA directory upload");
+        sinet_status st = measure_err(d, false, s, &err);
+        if (st != SINET_OK) return st;
+        window = err <= kPlaWindowErr;
     } else {
-        // error-bounded segmentation; the bound grows until the segments fit
         std::vector<float> c, g;
-        double target = E ? (double)E : 8.0;
-        for (;;) {
-            cone_segments(t->B, target, knots, c, g);
-            if (knots.size() <= max_segments) break;
-            target *= 2;
+        bool done = false;
+        if (E == 0) {
+            // the float32 evaluation and rounding can add one to a cone bound
+            for (double target : {6.0, 5.5, 5.0, 4.5, 4.0}) {
+                cone_segments(t->B, target, knots, c, g);
+                if (knots.size() > max_window) break;  // smaller targets need more
+                sinet_status st = set_segments(t, knots, c, g, s, &err);
+                if (st != SINET_OK) return st;
+                if (err <= kPlaWindowErr) {
+                    window = done = true;
+                    break;
+                }
+            }
+        }
+        if (!done) {
+            double target = E ? (double)E : 8.0;
+            for (;;) {
+                cone_segments(t->B, target, knots, c, g);
+                if (knots.size() <= max_segments) break;
+                target *= 2;
+            }
+            sinet_status st = set_segments(t, knots, c, g, s, &err);
+            if (st != SINET_OK) return st;
+            window = err <= kPlaWindowErr && knots.size() <= max_window;
         }
         S = (uint32_t)knots.size();
-        e = hipMemcpyAsync((void*)d.knot, knots.data(), 4ull * S, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync((void*)d.pla_c, c.data(), 4ull * S, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync((void*)d.pla_g, g.data(), 4ull * S, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     (void)hipEventRecord(e1, s);
-    if (e != hipSuccess) return check_hip(e, "PLA fit");
-    d.segments = S;
-    e = upload_radix(t, knots);
-    if (e != hipSuccess) return check_hip(e, "PLA directory upload");
-    uint32_t err = 0;
-    sinet_status st = measure_err(d, false, s, &err);
-    if (st != SINET_OK) return st;
+    (void)hipEventSynchronize(e1);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     d.max_err = err;
+    d.pla_window = window ? 1u : 0u;
     t->segments = S;
     r->max_err = err;
     r->max_err_untrained = err;

@@ -43,6 +43,7 @@ struct DevTable {
     const float* pla_g;         // [segments]
     const uint32_t* radix;      // PLA: first segment per radix bucket, u16 pairs
     uint32_t radix_bits;
+    uint32_t pla_window;        // PLA: max_err <= kPlaWindowErr, window search in B
     uint32_t filter_lds;        // 1: /16 filter staged in LDS and used
     const uint32_t* filter;     // [kFilterWords] 2-bit state per /16 block:
                                 // 0 all out, 1 all in, 2 cut by a boundary
@@ -61,8 +62,10 @@ struct DevTable {
 };
 
 constexpr uint32_t kFilterWords = 65536 / 16;  // 2 bits per /16 block
-constexpr uint32_t kPlaRadixBits = 14;
-constexpr uint32_t kInoutKind = 6;              // internal kind: label-only via the in/out index          // PLA segment directory: top 14 address bits
+constexpr uint32_t kPlaRadixBits = 12;          // PLA segment directory: top 12 address bits
+constexpr uint32_t kPlaWindowErr = 6;           // largest bound one 16-boundary window serves
+constexpr uint32_t kBTail = 20;                 // 0xFFFFFFFF past the padded boundaries
+constexpr uint32_t kInoutKind = 6;              // internal kind: label-only via the in/out index
 __host__ __device__ constexpr uint32_t radix_words(uint32_t bits) {
     return ((1u << bits) + 2) / 2;  // (2^bits + 1) u16 entries
 }
@@ -216,7 +219,7 @@ uint32_t batch_stage1_blocks_per_cu(uint32_t kind, size_t lds);
 
 // learned.hip
 sinet_status train_pla(sinet_table* t, uint32_t segments, uint32_t target_err, uint32_t max_segments,
-                       hipStream_t s, sinet_train_report* r);
+                       uint32_t max_window, hipStream_t s, sinet_train_report* r);
 hipError_t upload_radix(sinet_table* t, const std::vector<uint32_t>& knots);
 sinet_status train_mlp(sinet_table* t, const sinet_train_params* p, hipStream_t s,
                        sinet_train_report* r);

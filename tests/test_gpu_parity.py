@@ -488,6 +488,8 @@ def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, in
     _cmp_hist(sinet, out, (ec, eb, ed))
     if kind == "pla":
         assert tab.info().fallbacks == 0
+        # the bound is small enough for one 16-boundary window per lookup
+        assert tab.info().pla_window == 1 and tab.info().max_err <= 6
 
 
 def test_learned_forced_fallback_stays_exact(sinet, torch):
