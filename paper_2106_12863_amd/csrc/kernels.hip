@@ -340,6 +340,32 @@ __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, con
     }
 }
 
+// Column and table pointers always address device (global) memory.  Where the
+// kernels read them from a descriptor in memory (the batch kernels), the
+// compiler can no longer infer that and falls back to flat accesses, whose
+// waits are tied to LDS operations; these casts restore global accesses.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* glob(const T* q) {
+    return (const __attribute__((address_space(1))) T*)q;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glob(T* q) {
+    return (__attribute__((address_space(1))) T*)q;
+}
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint4 gload4(const uint32_t* q) {  // q 16-byte aligned
+    const u32x4_t v = *glob(reinterpret_cast<const u32x4_t*>(q));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ ulonglong2 gload2(const uint64_t* q) {
+    const u64x2_t v = *glob(reinterpret_cast<const u64x2_t*>(q));
+    return make_ulonglong2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore4(uint32_t* q, uint4 v) {
+    *glob(reinterpret_cast<u32x4_t*>(q)) = u32x4_t{v.x, v.y, v.z, v.w};
+}
+
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
@@ -417,14 +443,14 @@ __device__ __forceinline__ void account(const PassParams& p, const PrivHist& h, 
 // Label of session i (scalar path); stores label / institutions when asked.
 template <uint32_t KIND>
 __device__ __forceinline__ uint32_t label1(const PassParams& p, const LdsView& v, uint64_t i) {
-    const uint32_t a[2] = {p.src[i], p.dst[i]};
+    const uint32_t a[2] = {*glob(p.src + i), *glob(p.dst + i)};
     const bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
     uint32_t in[2], code[2];
     lookups<KIND, 2>(p.t, v, a, wc, in, code);
     const uint32_t lab = in[0] | (in[1] << 1);
-    if (p.label_out) p.label_out[i] = (uint8_t)lab;
-    if (p.src_inst) p.src_inst[i] = code[0] ? p.t.inst[code[0] - 1] : SINET_NO_INST;
-    if (p.dst_inst) p.dst_inst[i] = code[1] ? p.t.inst[code[1] - 1] : SINET_NO_INST;
+    if (p.label_out) *glob(p.label_out + i) = (uint8_t)lab;
+    if (p.src_inst) *glob(p.src_inst + i) = code[0] ? p.t.inst[code[0] - 1] : SINET_NO_INST;
+    if (p.dst_inst) *glob(p.dst_inst + i) = code[1] ? p.t.inst[code[1] - 1] : SINET_NO_INST;
     return lab;
 }
 
@@ -442,11 +468,11 @@ __device__ __forceinline__ void one_session(const PassParams& p, const LdsView& 
     }
     uint32_t lab;
     if constexpr (KIND == KK_LABEL_IN) {
-        lab = p.label_in[i] & 3u;
+        lab = *glob(p.label_in + i) & 3u;
     } else {
         lab = label1<KIND>(p, v, i);
     }
-    if constexpr (HM != H_NONE) account<HM>(p, h, lab, p.ts[i], p.bytes[i], d);
+    if constexpr (HM != H_NONE) account<HM>(p, h, lab, *glob(p.ts + i), *glob(p.bytes + i), d);
 }
 
 // Labels of four consecutive sessions starting at i from their loaded source
@@ -473,7 +499,7 @@ __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView&
         }
         if (p.label_out) {
             const uint32_t packed = lab[0] | (lab[1] << 8) | (lab[2] << 16) | (lab[3] << 24);
-            *reinterpret_cast<uint32_t*>(p.label_out + i) = packed;
+            *glob(reinterpret_cast<uint32_t*>(p.label_out + i)) = packed;
         }
         if (p.src_inst) {
             uint4 o;
@@ -481,7 +507,7 @@ __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView&
             o.y = sc[1] ? p.t.inst[sc[1] - 1] : SINET_NO_INST;
             o.z = sc[2] ? p.t.inst[sc[2] - 1] : SINET_NO_INST;
             o.w = sc[3] ? p.t.inst[sc[3] - 1] : SINET_NO_INST;
-            *reinterpret_cast<uint4*>(p.src_inst + i) = o;
+            gstore4(p.src_inst + i, o);
         }
         if (p.dst_inst) {
             uint4 o;
@@ -489,7 +515,7 @@ __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView&
             o.y = dc[1] ? p.t.inst[dc[1] - 1] : SINET_NO_INST;
             o.z = dc[2] ? p.t.inst[dc[2] - 1] : SINET_NO_INST;
             o.w = dc[3] ? p.t.inst[dc[3] - 1] : SINET_NO_INST;
-            *reinterpret_cast<uint4*>(p.dst_inst + i) = o;
+            gstore4(p.dst_inst + i, o);
         }
     }
 }
@@ -500,10 +526,10 @@ __device__ __forceinline__ void labels4(const PassParams& p, const LdsView& v, u
     uint4 s = make_uint4(0, 0, 0, 0), t = s;
     uint32_t l4 = 0;
     if constexpr (KIND == KK_LABEL_IN) {
-        l4 = *reinterpret_cast<const uint32_t*>(p.label_in + i);
+        l4 = *glob(reinterpret_cast<const uint32_t*>(p.label_in + i));
     } else {
-        s = *reinterpret_cast<const uint4*>(p.src + i);
-        t = *reinterpret_cast<const uint4*>(p.dst + i);
+        s = gload4(p.src + i);
+        t = gload4(p.dst + i);
     }
     labels4_from<KIND>(p, v, i, s, t, l4, lab);
 }
@@ -524,9 +550,9 @@ __device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView
     uint32_t lab[4];
     labels4<KIND>(p, v, i, lab);
     if constexpr (HM != H_NONE) {
-        const uint4 ts = *reinterpret_cast<const uint4*>(p.ts + i);
-        const ulonglong2 b01 = *reinterpret_cast<const ulonglong2*>(p.bytes + i);
-        const ulonglong2 b23 = *reinterpret_cast<const ulonglong2*>(p.bytes + i + 2);
+        const uint4 ts = gload4(p.ts + i);
+        const ulonglong2 b01 = gload2(p.bytes + i);
+        const ulonglong2 b23 = gload2(p.bytes + i + 2);
         account<HM>(p, h, lab[0], ts.x, b01.x, d);
         account<HM>(p, h, lab[1], ts.y, b01.y, d);
         account<HM>(p, h, lab[2], ts.z, b23.x, d);
@@ -542,7 +568,7 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) 
     uint32_t off = 0;
     auto copy = [&](const uint32_t* src, uint32_t n) -> const uint32_t* {
         uint32_t* dst = lds + off;
-        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) dst[k] = *glob(src + k);
         off += n;
         return dst;
     };
@@ -739,14 +765,14 @@ struct Raw4 {
 template <uint32_t KIND>
 __device__ __forceinline__ void load4(const PassParams& p, uint64_t i, Raw4& r) {
     if constexpr (KIND == KK_LABEL_IN) {
-        r.l4 = *reinterpret_cast<const uint32_t*>(p.label_in + i);
+        r.l4 = *glob(reinterpret_cast<const uint32_t*>(p.label_in + i));
     } else {
-        r.src = *reinterpret_cast<const uint4*>(p.src + i);
-        r.dst = *reinterpret_cast<const uint4*>(p.dst + i);
+        r.src = gload4(p.src + i);
+        r.dst = gload4(p.dst + i);
     }
-    r.ts = *reinterpret_cast<const uint4*>(p.ts + i);
-    r.b01 = *reinterpret_cast<const ulonglong2*>(p.bytes + i);
-    r.b23 = *reinterpret_cast<const ulonglong2*>(p.bytes + i + 2);
+    r.ts = gload4(p.ts + i);
+    r.b01 = gload2(p.bytes + i);
+    r.b23 = gload2(p.bytes + i + 2);
 }
 
 // LDS scratch of one stage-1 workgroup.
@@ -797,12 +823,12 @@ __device__ __forceinline__ void stage1_chunk(const PassParams& p, const PartWs& 
             bin[k] = 0;
             if (i < p.n) {
                 if constexpr (KIND == KK_LABEL_IN) {
-                    lab[k] = p.label_in[i] & 3u;
+                    lab[k] = *glob(p.label_in + i) & 3u;
                 } else {
                     lab[k] = label1<KIND>(p, v, i);
                 }
-                ts[k] = p.ts[i];
-                by[k] = p.bytes[i];
+                ts[k] = *glob(p.ts + i);
+                by[k] = *glob(p.bytes + i);
                 inw[k] = in_window(p, ts[k], bin[k]);
             }
         }
@@ -1284,7 +1310,15 @@ __device__ __forceinline__ void batch_stage1(const BatchArgs& a, const PartWs& w
             v = stage_lds<KIND>(s_bs.p.t, lds, &used);  // ends with a barrier
             staged = si;
         }
-        const BatchStreamDev& bs = s_bs;
+        // the descriptor in scalar registers for the item: read from LDS after
+        // every barrier it would cost an LDS round trip per use
+        BatchStreamDev bs;
+        {
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(&s_bs);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&bs);
+#pragma unroll
+            for (uint32_t k = 0; k < sizeof(BatchStreamDev) / 4; ++k) dst[k] = uniform_u32(src[k]);
+        }
         const PassParams& p = bs.p;
         Dropped d{};
         if (bs.priv) {
