@@ -171,7 +171,7 @@ def day_streams(sinet, wl, cols, tab, k, label, out):
     bins (its time range, padded by the jitter) and its own output."""
     import torch
     w = wl.window
-    per = (wl.n + k - 1) // k
+    per = ((wl.n + k - 1) // k + 2047) // 2048 * 2048   # whole 2048-session chunks
     streams, outs = [], []
     import sinetgen
     for i in range(k):

@@ -47,7 +47,6 @@ struct Prepared {
     std::vector<uint32_t> block_base;   // workspace block of each stream (+ total)
     uint64_t c_tot = 0;
     uint32_t k_tot = 0;
-    bool vec = true;
 };
 
 sinet_status prepare(const sinet_stream* st, uint32_t ns, Prepared& pr) {
@@ -89,7 +88,7 @@ sinet_status prepare(const sinet_stream* st, uint32_t ns, Prepared& pr) {
         pr.n_chunks[s] = (p.n + kChunk - 1) / kChunk;
         d.priv = (p.n_bins <= kPrivMaxBins &&
                   pr.lds_tab[s] + 48ull * p.n_bins + 16 <= kPrivLdsCap) ? 1u : 0u;
-        if (p.n && !vector_ok(p, p.t.kind, true)) pr.vec = false;
+        d.vec = vector_ok(p, p.t.kind, true) ? 1u : 0u;
     }
     uint64_t c = 0;
     uint64_t k = 0;
@@ -171,7 +170,7 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
     PartWs w = w0;
     w.n_chunks = pr.c_tot;
     w.n_blocks = pr.k_tot;
-    w.vec = pr.vec ? 1u : 0u;
+    w.vec = 0;  // unused by the batch kernels: vector loads are chosen per stream
     jobs.push_back({(unsigned long long*)(a + oCtl), (uint64_t)kinds.size()});
     jobs.push_back({(unsigned long long*)w.farcount, 1});
     if (pr.k_tot) jobs.push_back({(unsigned long long*)w.seg_count, (pr.k_tot + 1) / 2});

@@ -1331,7 +1331,7 @@ __device__ __forceinline__ void batch_stage1(const BatchArgs& a, const PartWs& w
                 h.c[k] = 0;
             }
             __syncthreads();
-            const bool vec = w.vec != 0;
+            const bool vec = bs.vec != 0;
             for (uint64_t c = item.y; c < item.z; ++c) {
                 const uint64_t g4 = c * (kChunk / 4) + tid;  // group of 4 sessions
                 if (vec && g4 * 4 + 4 <= p.n) {
@@ -1352,7 +1352,7 @@ __device__ __forceinline__ void batch_stage1(const BatchArgs& a, const PartWs& w
             }
             __syncthreads();
         } else {
-            const bool vec = w.vec != 0;
+            const bool vec = bs.vec != 0;
             auto full = [&](uint64_t c) { return vec && (c + 1) * kChunk <= p.n; };
             Raw4 cur{}, nxt{};
             uint64_t c = item.y;

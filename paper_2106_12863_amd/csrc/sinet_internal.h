@@ -132,6 +132,8 @@ struct BatchStreamDev {
     uint64_t chunk0;            // first workspace chunk (partitioned streams)
     uint32_t block0;            // first workspace block (partitioned streams)
     uint32_t priv;              // 1: histogram privatised in LDS, merged by atomics
+    uint32_t vec;               // 1: the stream's columns allow 16-byte loads
+    uint32_t pad;
 };
 
 struct BatchArgs {
