@@ -1893,9 +1893,39 @@ int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n)
     return 3;  // partitioned
 }
 
+// The columns advanced by off sessions.
+static PassParams advance(const PassParams& p, uint64_t off) {
+    PassParams q = p;
+    q.n = p.n - off;
+    auto a32 = [&](const uint32_t* x) { return x ? x + off : x; };
+    q.ts = a32(p.ts);
+    q.src = a32(p.src);
+    q.dst = a32(p.dst);
+    q.bytes = p.bytes ? p.bytes + off : nullptr;
+    q.label_in = p.label_in ? p.label_in + off : nullptr;
+    q.label_out = p.label_out ? p.label_out + off : nullptr;
+    q.src_inst = p.src_inst ? p.src_inst + off : nullptr;
+    q.dst_inst = p.dst_inst ? p.dst_inst + off : nullptr;
+    return q;
+}
+
 sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s) {
     const uint32_t kind = (mode & PASS_LABEL_IN) ? (uint32_t)KK_LABEL_IN : p.t.kind;
     if (p.n == 0) return SINET_OK;
+    if (!vector_ok(p, kind, true)) {
+        // columns that all sit h sessions short of 16-byte alignment (slices of
+        // aligned arrays): the aligned rest takes the vector path, then the first
+        // h sessions are added by the atomic pass
+        for (uint64_t h = 1; h < 4 && h < p.n; ++h) {
+            if (!vector_ok(advance(p, h), kind, true)) continue;
+            sinet_status st = run_hist(advance(p, h), mode, accumulate, s);
+            if (st != SINET_OK) return st;
+            PassParams head = p;
+            head.n = h;
+            FarList none{};
+            return launch_k_pass(head, kind, H_ATOMIC, false, none, 0, s);
+        }
+    }
     count_timed_call();
     const int strat = hist_strategy(p.t, kind, p.n_bins, p.n);
     if (strat == H_PRIVATE) {
