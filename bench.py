@@ -100,6 +100,17 @@ def time_calls(torch, fn, steps, warmup, sinet=None):
     return sum(dev) / len(dev), min(dev), wall * 1e3 / steps, phases
 
 
+def copy_ceiling(torch, gb=2.0, reps=5):
+    """Read + write GB/s of a plain device-to-device copy of gb GB: the
+    practical bandwidth ceiling the fractions are also reported against."""
+    n = int(gb * 1e9) // 16
+    x = torch.empty(n, 2, dtype=torch.int64, device="cuda")
+    y = torch.empty_like(x)
+    ms, _, _, _ = time_calls(torch, lambda: y.copy_(x), reps, 1)
+    del x, y
+    return 2 * 16 * n / (ms * 1e-3) / 1e9
+
+
 def kernel_roofline(phases, n, n_bins, steps, workload):
     """Roofline of the dominant kernel of the step from the library's phase
     events over the timed calls: the stage-1 kernel (read ts/src/dst/bytes,
@@ -241,6 +252,10 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     r = results[head]
     alg_bytes = BYTES_PER_SESSION * wl.n + BYTES_PER_BIN * w.n_bins
     roof = kernel_roofline(r.get("_phases"), wl.n, w.n_bins, args.steps, wl.name)
+    copy_gbs = copy_ceiling(torch)
+    if roof is not None:
+        roof["copy_ceiling_gbs"] = copy_gbs
+        roof["frac_of_copy"] = roof["achieved"] / copy_gbs
     line = {
         "metric": METRIC, "value": r["sessions_per_s"], "unit": "sessions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -252,7 +267,8 @@ def bench_day(args, torch, sinet, sinetgen, gg):
         "roofline": roof,
         "step_roofline": {"alg_bytes": alg_bytes, "ms": r["ms_per_step"],
                           "achieved": alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9,
-                          "frac": alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                          "frac": alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "frac_of_copy": alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / copy_gbs},
         "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("wall_ms", "_phases")}
                   for k, v in results.items()},
     }

@@ -248,3 +248,41 @@ def test_pipeline_equals_classify_then_histogram():
     assert np.array_equal(lab, lab2)
     c2, by2, dr2 = oracle.histogram(s["ts"], s["bytes"], lab2, 0, 1, 86_400_000 // 1000)
     assert np.array_equal(c, c2) and np.array_equal(by, by2) and np.array_equal(dr, dr2)
+
+
+def test_label_bits_equal_institution_presence():
+    """Bit 0 of the label is set exactly when the source has a longest match
+    (an institution id), bit 1 likewise for the destination."""
+    import sinetgen
+    wl = sinetgen.config(2, n=30_000)
+    s = sinetgen.sessions(wl, start=0, stop=30_000)
+    lab, si, di = oracle.classify(wl.pbase, wl.plen, s["src"], s["dst"])
+    assert np.array_equal((lab & 1) == 1, si != np.uint32(oracle.NO_INST))
+    assert np.array_equal((lab >> 1) == 1, di != np.uint32(oracle.NO_INST))
+
+
+def test_dense_bins_equal_the_papers_sparse_maps():
+    """The paper's outputs are <timestamp,count> and <timestamp,bytes> maps
+    per direction; built here with plain dictionaries, they are exactly the
+    non-zero bins of the dense label-major histogram."""
+    import sinetgen
+    wl = sinetgen.config(1, n=5_000)
+    s = sinetgen.sessions(wl)
+    t0, width, n_bins = 500, 7, 8_000
+    lab, c, by, dr = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"], s["bytes"],
+                                     t0, width, n_bins)
+    count_map = [dict() for _ in range(4)]
+    bytes_map = [dict() for _ in range(4)]
+    for i in range(wl.n):
+        t = int(s["ts"][i])
+        if t < t0 or (t - t0) // width >= n_bins:
+            continue
+        key = (t - t0) // width
+        l = int(lab[i])
+        count_map[l][key] = count_map[l].get(key, 0) + 1
+        bytes_map[l][key] = (bytes_map[l].get(key, 0) + int(s["bytes"][i])) % (1 << 64)
+    for l in range(4):
+        nz = np.nonzero(c[l])[0]
+        assert sorted(count_map[l]) == nz.tolist()
+        assert all(count_map[l][k] == int(c[l][k]) for k in nz)
+        assert all(bytes_map[l][k] == int(by[l][k]) for k in nz)
