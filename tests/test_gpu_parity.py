@@ -383,13 +383,16 @@ def test_intervals_and_positions(sinet, torch, cfg):
 
 
 # ---------------------------------------------------------- full-size day
-def test_full_day_sampled_and_invariants(sinet, torch):
-    """Config 2 at its full size (1e8 sessions, 86.4 M 1-ms bins), the launch
-    the benchmark times: sampled labels and bins recomputed by the oracle,
-    conservation over every bin."""
+@pytest.mark.parametrize("cfg", [2, 5])
+def test_full_day_sampled_and_invariants(sinet, torch, cfg):
+    """The 1e8-session day (1,024 prefixes) and the 1.6e9-session day
+    (200,000 prefixes), both with 86.4 M 1-ms bins, in the launch the
+    benchmark times: sampled labels and bins recomputed by the oracle,
+    conservation over every bin; on the large day the learned PLA form must
+    give the same labels and bins as the plain form."""
     import sinetgen.gpu as gg
-    wl = sinetgen.config(2)
-    _say("full day", wl.n)
+    wl = sinetgen.config(cfg)
+    _say("full day", cfg, wl.n)
     cols = gg.alloc_and_fill(wl)
     w = wl.window
     tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch")
@@ -425,6 +428,15 @@ def test_full_day_sampled_and_invariants(sinet, torch):
         got_b = sinet.to_host_u64(b[:, tb])
         assert np.array_equal(got_c, ec[:, 0]), tb
         assert np.array_equal(got_b, eb[:, 0]), tb
+    if cfg == 5:
+        pla = sinet.Table(wl.pbase, wl.plen, kind="pla", inout_index=False)
+        pla.train()
+        lab2, (c2, b2, d2) = sinet.pipeline(pla, cols["ts"], cols["src"], cols["dst"],
+                                            cols["bytes"], w.t0, w.width, w.n_bins)
+        torch.cuda.synchronize()
+        assert pla.info().pla_window == 1 and pla.info().fallbacks == 0
+        assert torch.equal(lab2, lab)
+        assert torch.equal(c2, c) and torch.equal(b2, b) and torch.equal(d2, d)
 
 
 # ---------------------------------------------------------------- learned
