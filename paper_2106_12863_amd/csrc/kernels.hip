@@ -1113,14 +1113,32 @@ __device__ __forceinline__ void stage2_describe(const PartWs& w, Stage2Shared& s
     if (threadIdx.x == 0) sh.nseg[d] = n;
 }
 
+// Bin pairs are written with non-temporal 16-byte stores: the histogram is
+// written once and not read back by this pass.
+__device__ __forceinline__ void store_pair(unsigned long long* q, unsigned long long x,
+                                           unsigned long long y) {
+    __builtin_nontemporal_store(u64x2_t{x, y}, glob(reinterpret_cast<u64x2_t*>(q)));
+}
+
 // Write the block's bins (two consecutive bins per lane, 16-byte stores when
 // the label rows are 16-byte aligned, which holds when n_bins is even) and
-// clear the accumulators it read.
-__device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t) {
+// clear the accumulators it read.  A block without records (empty) writes
+// zeros without touching the accumulators, which are already clear.
+__device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t, bool empty) {
     const uint64_t b0 = (uint64_t)t.blk * kBlockBins;
     const bool pairs =
         (t.n_bins & 1u) == 0 && (((uintptr_t)t.count | (uintptr_t)t.hbytes) & 15u) == 0;
-    if (pairs) {
+    if (pairs && empty && !t.accumulate) {
+        for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
+            const uint32_t e = 2 * k;
+            const uint32_t lab = e / kBlockBins, off = e % kBlockBins;
+            const uint64_t bin = b0 + off;
+            if (bin >= t.n_bins) continue;
+            const uint64_t o = (uint64_t)lab * t.n_bins + bin;
+            store_pair(t.count + o, 0ull, 0ull);
+            store_pair(t.hbytes + o, 0ull, 0ull);
+        }
+    } else if (pairs) {
         for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
             const uint32_t e = 2 * k;
             const uint32_t lab = e / kBlockBins, off = e % kBlockBins;
@@ -1141,8 +1159,8 @@ __device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t
                 b.x += ob.x;
                 b.y += ob.y;
             }
-            *reinterpret_cast<ulonglong2*>(t.count + o) = c;
-            *reinterpret_cast<ulonglong2*>(t.hbytes + o) = b;
+            store_pair(t.count + o, c.x, c.y);
+            store_pair(t.hbytes + o, b.x, b.y);
         }
     } else {
         for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
@@ -1188,6 +1206,7 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
         n0 = w.seg_off[gn];
         n1 = w.seg_off[gn + 1];
     }
+    BlockOut cur = out(g);  // where the current block's bins go (found one block ahead)
     for (uint32_t d = 0; g < nb; g = gn, gn += G, d ^= 1u) {
         __syncthreads();  // descriptors of g in buffer d, accumulators clear
         // in flight during this block: the next block's descriptors and the
@@ -1201,6 +1220,7 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
             m0 = w.seg_off[gnn];
             m1 = w.seg_off[gnn + 1];
         }
+        const BlockOut nxt = gn < nb ? out(gn) : cur;  // its lookup overlaps this block
         stage2_segments(w, sh, d);
         // blocks with more than kSegMax segments (unsorted input): further
         // batches through the same buffer
@@ -1212,7 +1232,7 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
             stage2_segments(w, sh, d);
         }
         __syncthreads();  // accumulation complete
-        stage2_write(sh, out(g));
+        stage2_write(sh, cur, s0 == s1);
         if (gn < nb) {
             const uint32_t e = d ^ 1u;  // last read before this block's first barrier
             if (tid < nn) {
@@ -1227,6 +1247,7 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
         }
         n0 = m0;
         n1 = m1;
+        cur = nxt;
     }
 }
 
