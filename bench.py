@@ -44,9 +44,9 @@ DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched"
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
 COUNTER_TRAFFIC = {
-    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "f86265f80aa9a95f",
+    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "6d834efc3a596c07",
                  "bytes": 40.32e9},
-    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "f86265f80aa9a95f",
+    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "6d834efc3a596c07",
                  "bytes": 12.98e9},
 }
 KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")
@@ -275,7 +275,7 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     for k, v in results.items():
         line["forms"][k]["hbm_frac"] = alg_bytes / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     if not args.no_cpu:
-        sample = args.cpu_sample or (60_000_000 if wl.n_prefix <= 4096 else 30_000_000)
+        sample = args.cpu_sample or (60_000_000 if wl.n_prefix <= 4096 else 40_000_000)
         line["cpu_baseline"] = cpu_baseline(wl, cols, sinet, sample)
     return line
 
