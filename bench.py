@@ -100,13 +100,14 @@ def time_calls(torch, fn, steps, warmup, sinet=None):
     return sum(dev) / len(dev), min(dev), wall * 1e3 / steps, phases
 
 
-def copy_ceiling(torch, gb=2.0, reps=5):
-    """Read + write GB/s of a plain device-to-device copy of gb GB: the
-    practical bandwidth ceiling the fractions are also reported against."""
+def copy_ceiling(torch, gb=4.0, reps=10):
+    """Read + write GB/s of a plain device-to-device copy of gb GB (the best
+    of reps): the practical bandwidth ceiling the fractions are also reported
+    against."""
     n = int(gb * 1e9) // 16
     x = torch.empty(n, 2, dtype=torch.int64, device="cuda")
     y = torch.empty_like(x)
-    ms, _, _, _ = time_calls(torch, lambda: y.copy_(x), reps, 1)
+    _, ms, _, _ = time_calls(torch, lambda: y.copy_(x), reps, 2)
     del x, y
     return 2 * 16 * n / (ms * 1e-3) / 1e9
 
