@@ -936,7 +936,7 @@ __global__ void __launch_bounds__(kStage1Block, 4) k_stage1(PassParams p, PartWs
     const uint32_t tid = threadIdx.x;
     const uint64_t n_chunks = w.n_chunks;
     uint32_t iter = 0;
-    // a chunk is "full" when its 4096 sessions exist and vector loads are allowed
+    // a chunk is "full" when its kChunk sessions exist and vector loads are allowed
     auto full = [&](uint64_t c) { return w.vec && (c + 1) * kChunk <= p.n; };
     Raw4 cur{}, nxt{};
     uint64_t c = blockIdx.x;
