@@ -98,18 +98,6 @@ __device__ __forceinline__ void upper_last_n(const uint32_t* arr, uint32_t n, co
     }
 }
 
-// Same over per-address windows arr[base[q] .. base[q] + n) (absolute result).
-template <int N>
-__device__ __forceinline__ void upper_last_based(const uint32_t* arr, uint32_t n, const uint32_t* a,
-                                                 uint32_t* lo) {
-    while (n > 1) {
-        const uint32_t half = n >> 1;
-#pragma unroll
-        for (int q = 0; q < N; ++q) lo[q] = (arr[lo[q] + half] <= a[q]) ? lo[q] + half : lo[q];
-        n -= half;
-    }
-}
-
 __device__ __forceinline__ uint32_t radix_entry(const uint32_t* radix, uint32_t i) {
     return (radix[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu;
 }
@@ -292,10 +280,6 @@ __device__ __forceinline__ uint32_t scan_owner(const DevTable& t, const LdsView&
 // address.  Label-only lookups first consult the /16 filter: a block that no
 // boundary cuts is entirely in or entirely out, which answers most addresses
 // from LDS; only addresses in cut blocks run the table's search.
-__device__ __forceinline__ uint32_t u16_at(const uint32_t* w, uint32_t i) {
-    return (w[i >> 1] >> ((i & 1u) * 16)) & 0xFFFFu;
-}
-
 template <uint32_t KIND, int N>
 __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, const uint32_t* a,
                                         bool want_code, uint32_t* in, uint32_t* code) {
