@@ -286,3 +286,17 @@ def test_dense_bins_equal_the_papers_sparse_maps():
         assert sorted(count_map[l]) == nz.tolist()
         assert all(count_map[l][k] == int(c[l][k]) for k in nz)
         assert all(bytes_map[l][k] == int(by[l][k]) for k in nz)
+
+
+def test_scan_equals_hash_on_the_200k_table_sample():
+    """The per-length hash mode (used to time and check the large tables)
+    equals Algorithm 1's scan over all 200,000 prefixes on a sample of the
+    large day's addresses, institutions included."""
+    import sinetgen
+    wl = sinetgen.config(4, n=4_000)
+    s = sinetgen.sessions(wl, start=0, stop=wl.n)
+    r1 = oracle.classify(wl.pbase, wl.plen, s["src"], s["dst"], mode="scan")
+    r2 = oracle.classify(wl.pbase, wl.plen, s["src"], s["dst"], mode="hash")
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+    assert 0 < int(np.count_nonzero(r1[0])) < wl.n   # both in- and out-of-table addresses
