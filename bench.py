@@ -19,7 +19,8 @@ Forms timed on the same resident day (the first is the headline value):
   mlp          learned: 1-16-1 ReLU MLP, same window search
   (every form but plain runs its own search for every address)
   batched      the day cut into time-ordered streams, one graph launch
-               (table with the learned PLA and the in/out index)
+               (table with the learned PLA and the in/out index: labels from the index)
+  batched_pla  the same with the learned PLA answering every lookup
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5|4|2|3]
                     [--forms plain,bsearch,...] [--no-cpu]
@@ -39,7 +40,7 @@ METRIC = "sessions/sec classify+histogram on 1 GPU, % HBM roofline; learned vs p
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SESSION = 21   # ts 4 + src 4 + dst 4 + bytes 8 read, label 1 written
 BYTES_PER_BIN = 64       # 4 labels x (count 8 + bytes 8) written once
-DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched"
+DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched,batched_pla"
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of the
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
@@ -214,8 +215,10 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     out = sinet.new_hist(w.n_bins)
     results = {}
     for form in forms:
-        if form == "batched":
-            tab = sinet.Table(wl.pbase, wl.plen, kind="pla")
+        if form in ("batched", "batched_pla"):
+            # batched: labels from the in/out index of the PLA table;
+            # batched_pla: labels from the learned PLA lookup itself
+            tab = sinet.Table(wl.pbase, wl.plen, kind="pla", inout_index=(form == "batched"))
             rep = tab.train()
             streams, outs = day_streams(sinet, wl, cols, tab, args.day_streams, label, out)
             tune = sinet.autotune(streams)
@@ -230,7 +233,7 @@ def bench_day(args, torch, sinet, sinetgen, gg):
                                                cols["bytes"], w.t0, w.width, w.n_bins,
                                                label=label, out=out))
         ms, ms_min, wall, phases = time_calls(torch, fn, args.steps, args.warmup,
-                                              None if form == "batched" else sinet)
+                                              None if form.startswith("batched") else sinet)
         info = tab.info()
         results[form] = {"sessions_per_s": wl.n / (ms * 1e-3), "ms_per_step": ms, "ms_min": ms_min,
                          "wall_ms": wall, "kind": sinet.KIND_NAMES[info.kind],
@@ -243,7 +246,7 @@ def bench_day(args, torch, sinet, sinetgen, gg):
                 k[:-3]: phases[k] / args.steps
                 for k in ("lookup_ms", "stage1_ms", "index_ms", "stage2_ms", "far_ms")}
             results[form]["_phases"] = phases
-        if form == "batched":
+        if form.startswith("batched"):
             results[form]["tune"] = {"block": tune.block, "chunk": tune.chunk, "grid": tune.grid}
             results[form]["streams"] = len(streams)
             del plan, streams, outs

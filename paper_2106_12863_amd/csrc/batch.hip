@@ -38,8 +38,15 @@ namespace {
 constexpr uint32_t kPrivMaxBins = 1024;            // LDS-private histograms up to this size
 constexpr size_t kPrivLdsCap = 150 * 1024;         // table + private bins per workgroup
 
+constexpr uint32_t kNoLookup = 0xFFFFFFFFu;
+
 struct Prepared {
     std::vector<BatchStreamDev> desc;
+    std::vector<BatchStreamDev> ldesc;  // lookup-pass descriptor of split streams
+    std::vector<uint32_t> lkind;        // lookup kind of split streams, else kNoLookup
+    std::vector<size_t> lds_look;       // table LDS of the lookup pass
+    std::vector<uint64_t> tmp_off;      // offset of a plan-owned label buffer, or ~0
+    uint64_t tmp_bytes = 0;
     std::vector<uint32_t> kind;         // kernel kind per stream
     std::vector<size_t> lds_tab;        // table LDS per stream
     std::vector<uint64_t> n_chunks;     // chunks of each stream (sessions / kChunk)
@@ -52,6 +59,10 @@ struct Prepared {
 sinet_status prepare(const sinet_stream* st, uint32_t ns, Prepared& pr) {
     if (!st || ns == 0) return fail(SINET_ERR_INVALID_ARG, "no streams");
     pr.desc.resize(ns);
+    pr.ldesc.resize(ns);
+    pr.lkind.assign(ns, kNoLookup);
+    pr.lds_look.assign(ns, 0);
+    pr.tmp_off.assign(ns, ~0ull);
     pr.kind.resize(ns);
     pr.lds_tab.resize(ns);
     pr.n_chunks.resize(ns);
@@ -89,6 +100,24 @@ sinet_status prepare(const sinet_stream* st, uint32_t ns, Prepared& pr) {
         d.priv = (p.n_bins <= kPrivMaxBins &&
                   pr.lds_tab[s] + 48ull * p.n_bins + 16 <= kPrivLdsCap) ? 1u : 0u;
         d.vec = vector_ok(p, p.t.kind, true) ? 1u : 0u;
+        // lookups that walk global memory: a lookup pass stores the labels (in
+        // the stream's label output, or a plan-owned buffer when it has none),
+        // stage 1 reads them
+        if (!d.priv && p.n && lookup_splits(p.t)) {
+            pr.lkind[s] = p.t.kind;
+            pr.lds_look[s] = p.t.lds_bytes;
+            BatchStreamDev& l = pr.ldesc[s];
+            l = d;
+            if (!x.label) {
+                pr.tmp_off[s] = pr.tmp_bytes;
+                pr.tmp_bytes += (p.n + 255) & ~255ull;
+            }
+            pr.kind[s] = kLabelInKind;
+            pr.lds_tab[s] = 0;
+            d.p.t.kind = kLabelInKind;
+            d.p.label_in = x.label;  // or the plan buffer, set when the arena exists
+            d.p.label_out = nullptr;
+        }
     }
     uint64_t c = 0;
     uint64_t k = 0;
@@ -142,6 +171,23 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
             items[g].push_back(make_uint4(s, (uint32_t)c0, (uint32_t)c1, 0u));
         }
     }
+    // lookup-pass groups of the split streams
+    std::vector<uint32_t> lkinds;
+    for (uint32_t s = 0; s < ns; ++s)
+        if (pr.lkind[s] != kNoLookup &&
+            std::find(lkinds.begin(), lkinds.end(), pr.lkind[s]) == lkinds.end())
+            lkinds.push_back(pr.lkind[s]);
+    std::vector<std::vector<uint4>> litems(lkinds.size());
+    std::vector<size_t> lgroup_lds(lkinds.size(), 8);
+    for (uint32_t s = 0; s < ns; ++s) {
+        if (pr.lkind[s] == kNoLookup) continue;
+        const size_t g = std::find(lkinds.begin(), lkinds.end(), pr.lkind[s]) - lkinds.begin();
+        lgroup_lds[g] = std::max(lgroup_lds[g], pr.lds_look[s] + 16);
+        for (uint64_t c0 = 0; c0 < pr.n_chunks[s]; c0 += item_chunks) {
+            const uint64_t c1 = std::min<uint64_t>(pr.n_chunks[s], c0 + item_chunks);
+            litems[g].push_back(make_uint4(s, (uint32_t)c0, (uint32_t)c1, 0u));
+        }
+    }
     // clears: queue heads, far count, directory counts, dropped, private bins
     std::vector<ZeroJob> jobs;
 
@@ -151,9 +197,14 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
     const size_t oDesc = take(sizeof(BatchStreamDev) * ns);
     std::vector<size_t> oItems(kinds.size());
     for (size_t g = 0; g < kinds.size(); ++g) oItems[g] = take(sizeof(uint4) * std::max<size_t>(1, items[g].size()));
+    const size_t oLDesc = take(sizeof(BatchStreamDev) * ns);
+    std::vector<size_t> oLItems(lkinds.size());
+    for (size_t g = 0; g < lkinds.size(); ++g) oLItems[g] = take(sizeof(uint4) * litems[g].size());
+    const size_t oTmp = take(pr.tmp_bytes);
     const size_t oCb = take(8ull * (ns + 1));
     const size_t oBb = take(4ull * (ns + 1));
-    const size_t oCtl = take(8ull * kinds.size());
+    const size_t n_ctl = kinds.size() + lkinds.size();  // queue heads: stage 1, then lookups
+    const size_t oCtl = take(8ull * n_ctl);
     const size_t ws_bytes = part_ws_bytes(std::max<uint64_t>(1, pr.c_tot) * kChunk,
                                           std::max<uint32_t>(1, pr.k_tot) * kBlockBins);
     const size_t oWs = take(ws_bytes);
@@ -171,7 +222,18 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
     w.n_chunks = pr.c_tot;
     w.n_blocks = pr.k_tot;
     w.vec = 0;  // unused by the batch kernels: vector loads are chosen per stream
-    jobs.push_back({(unsigned long long*)(a + oCtl), (uint64_t)kinds.size()});
+    // label buffers of the split streams, and the vector-load choice now that
+    // every address is known
+    for (uint32_t s = 0; s < ns; ++s) {
+        if (pr.lkind[s] == kNoLookup) continue;
+        BatchStreamDev& d = pr.desc[s];
+        BatchStreamDev& l = pr.ldesc[s];
+        if (pr.tmp_off[s] != ~0ull) d.p.label_in = (const uint8_t*)(a + oTmp + pr.tmp_off[s]);
+        l.p.label_out = const_cast<uint8_t*>(d.p.label_in);
+        l.vec = vector_ok(l.p, l.p.t.kind, false) ? 1u : 0u;
+        d.vec = vector_ok(d.p, kLabelInKind, true) ? 1u : 0u;
+    }
+    jobs.push_back({(unsigned long long*)(a + oCtl), (uint64_t)n_ctl});
     jobs.push_back({(unsigned long long*)w.farcount, 1});
     if (pr.k_tot) jobs.push_back({(unsigned long long*)w.seg_count, (pr.k_tot + 1) / 2});
     for (uint32_t s = 0; s < ns; ++s) {
@@ -183,6 +245,11 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
         }
     }
     e = hipMemcpy(a + oDesc, pr.desc.data(), sizeof(BatchStreamDev) * ns, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(a + oLDesc, pr.ldesc.data(), sizeof(BatchStreamDev) * ns, hipMemcpyHostToDevice);
+    for (size_t g = 0; e == hipSuccess && g < lkinds.size(); ++g)
+        e = hipMemcpy(a + oLItems[g], litems[g].data(), sizeof(uint4) * litems[g].size(),
+                      hipMemcpyHostToDevice);
     for (size_t g = 0; e == hipSuccess && g < kinds.size(); ++g)
         if (!items[g].empty())
             e = hipMemcpy(a + oItems[g], items[g].data(), sizeof(uint4) * items[g].size(),
@@ -210,6 +277,19 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
         grids[g] = tune.grid ? tune.grid : device_cu_count() * occ;
     }
 
+    std::vector<BatchArgs> largs(lkinds.size());
+    for (size_t g = 0; g < lkinds.size(); ++g) {
+        BatchArgs& ba = largs[g];
+        memset(&ba, 0, sizeof(ba));
+        ba.streams = (const BatchStreamDev*)(a + oLDesc);
+        ba.items = (const uint4*)(a + oLItems[g]);
+        ba.n_items = (uint32_t)litems[g].size();
+        ba.n_streams = ns;
+        ba.counter = (uint32_t*)(a + oCtl + 8 * (kinds.size() + g));
+        ba.chunk_base = (const uint64_t*)(a + oCb);
+        ba.block_base = (const uint32_t*)(a + oBb);
+    }
+
     // capture
     e = hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking);
     if (e != hipSuccess) return check_hip(e, "capture stream");
@@ -217,6 +297,8 @@ sinet_status build_plan(const sinet_stream* st, uint32_t ns, const sinet_tune& t
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return check_hip(e, "begin capture");
     rc = launch_zero_jobs((const ZeroJob*)(a + oJobs), (uint32_t)jobs.size(), cs);
+    for (size_t g = 0; rc == SINET_OK && g < lkinds.size(); ++g)
+        rc = launch_batch_lookup(lkinds[g], largs[g], lgroup_lds[g], 0, cs);
     for (size_t g = 0; rc == SINET_OK && g < kinds.size(); ++g)
         if (args[g].n_items) rc = launch_batch_stage1(kinds[g], args[g], w, group_lds[g], grids[g], cs);
     if (rc == SINET_OK && pr.k_tot) rc = launch_scan_fill(w, cs);

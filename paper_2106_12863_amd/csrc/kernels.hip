@@ -50,6 +50,7 @@ enum KernelKind : uint32_t {
     KK_INOUT = kInoutKind,  // label-only lookups through the in/out index
     KK_LABEL_IN = 100       // histogram of given labels
 };
+static_assert(KK_LABEL_IN == kLabelInKind && KK_INOUT == kInoutKind, "internal kinds");
 
 constexpr int kXcds = 8;
 constexpr int kMaxBlock = 1024;
@@ -1447,6 +1448,77 @@ __global__ void __launch_bounds__(kMaxBlock) k_batch_far(BatchArgs a, PartWs w) 
     }
 }
 
+// Batched lookup pass: streams whose lookups walk global memory store their
+// labels first, as the single-stream path does, and stage 1 reads them (one
+// byte per session) instead of stalling its barriers on the lookups.  Work
+// items as in batch stage 1; a workgroup restages the table only when the
+// stream changes; the next four sessions' addresses are loaded before the
+// current ones are looked up.
+template <uint32_t KIND>
+__global__ void __launch_bounds__(kMaxBlock) k_batch_lookup(BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ uint32_t s_item;
+    __shared__ BatchStreamDev s_bs;
+    const uint32_t tid = threadIdx.x;
+    uint32_t staged = 0xFFFFFFFFu;
+    LdsView v{};
+    uint32_t used = 0;
+    const PrivHist h{nullptr, nullptr};
+    for (;;) {
+        __syncthreads();  // every lane is done with the previous item
+        if (tid == 0) s_item = atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const uint32_t it = uniform_u32(s_item);
+        if (it >= a.n_items) break;
+        const uint4 item = a.items[it];
+        const uint32_t si = uniform_u32(item.x);
+        if (si != staged) {
+            constexpr uint32_t kWords = sizeof(BatchStreamDev) / 4;
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(a.streams + si);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&s_bs);
+            for (uint32_t k = tid; k < kWords; k += blockDim.x) dst[k] = src[k];
+            __syncthreads();
+            v = stage_lds<KIND>(s_bs.p.t, lds, &used);  // ends with a barrier
+            staged = si;
+        }
+        BatchStreamDev bs;
+        {
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(&s_bs);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&bs);
+#pragma unroll
+            for (uint32_t k = 0; k < sizeof(BatchStreamDev) / 4; ++k) dst[k] = uniform_u32(src[k]);
+        }
+        const PassParams& p = bs.p;
+        const uint64_t groups = (p.n + 3) / 4;
+        const uint64_t g0 = (uint64_t)item.y * (kChunk / 4);
+        const uint64_t g1 = min((uint64_t)item.z * (kChunk / 4), groups);
+        auto full = [&](uint64_t g) { return bs.vec && g * 4 + 4 <= p.n; };
+        uint4 cs = make_uint4(0, 0, 0, 0), cd = cs, ns = cs, nd = cs;
+        uint64_t g = g0 + tid;
+        if (g < g1 && full(g)) {
+            cs = gload4(p.src + g * 4);
+            cd = gload4(p.dst + g * 4);
+        }
+        for (; g < g1; g += blockDim.x) {
+            const uint64_t gn = g + blockDim.x;
+            if (gn < g1 && full(gn)) {
+                ns = gload4(p.src + gn * 4);
+                nd = gload4(p.dst + gn * 4);
+            }
+            if (full(g)) {
+                uint32_t lab[4];
+                labels4_from<KIND>(p, v, g * 4, cs, cd, 0u, lab);
+            } else {
+                Dropped d{};
+                for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
+                    one_session<KIND, H_NONE>(p, v, h, i, d);
+            }
+            cs = ns;
+            cd = nd;
+        }
+    }
+}
+
 __global__ void k_zero_jobs(const ZeroJob* __restrict__ jobs, uint32_t n_jobs) {
     for (uint32_t j = blockIdx.x; j < n_jobs; j += gridDim.x) {
         const ZeroJob z = jobs[j];
@@ -1798,6 +1870,7 @@ static BatchFn pick_batch_stage1(uint32_t kind) {
         case KK_PLA: return k_batch_stage1<KK_PLA>;
         case KK_MLP: return k_batch_stage1<KK_MLP>;
         case KK_INOUT: return k_batch_stage1_o4<KK_INOUT>;
+        case KK_LABEL_IN: return k_batch_stage1_o4<KK_LABEL_IN>;
         default: return nullptr;
     }
 }
@@ -1810,8 +1883,33 @@ static BatchFn pick_batch_far(uint32_t kind) {
         case KK_PLA: return k_batch_far<KK_PLA>;
         case KK_MLP: return k_batch_far<KK_MLP>;
         case KK_INOUT: return k_batch_far<KK_INOUT>;
+        case KK_LABEL_IN: return k_batch_far<KK_LABEL_IN>;
         default: return nullptr;
     }
+}
+
+using LookupFn = void (*)(BatchArgs);
+
+static LookupFn pick_batch_lookup(uint32_t kind) {
+    switch (kind) {
+        case KK_BSEARCH: return k_batch_lookup<KK_BSEARCH>;
+        case KK_TRIE: return k_batch_lookup<KK_TRIE>;
+        case KK_PLA: return k_batch_lookup<KK_PLA>;
+        case KK_MLP: return k_batch_lookup<KK_MLP>;
+        default: return nullptr;
+    }
+}
+
+sinet_status launch_batch_lookup(uint32_t kind, const BatchArgs& a, size_t lds, uint32_t grid,
+                                 hipStream_t s) {
+    LookupFn fn = pick_batch_lookup(kind);
+    if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no batch lookup kernel for this kind");
+    if (lds + sizeof(BatchStreamDev) + 16 > 160 * 1024)
+        return fail(SINET_ERR_UNSUPPORTED, "batch needs more LDS than a CU has");
+    const int block = lds > 40 * 1024 ? kMaxBlock : 256;
+    if (grid == 0) grid = device_cu_count() * blocks_per_cu((const void*)fn, block, lds);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a);
+    return check_hip(hipGetLastError(), "batch lookup launch");
 }
 
 uint32_t batch_stage1_blocks_per_cu(uint32_t kind, size_t lds) {
@@ -1898,6 +1996,13 @@ int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n)
     return 3;  // partitioned
 }
 
+// Lookups that walk global memory (trie, learned windows, binary searches
+// with a global leaf) run as their own pass before stage 1.
+bool lookup_splits(const DevTable& t) {
+    return t.kind == KK_TRIE || t.kind == KK_PLA || t.kind == KK_MLP ||
+           (t.kind == KK_BSEARCH && t.top_log2 > 0);
+}
+
 // The columns advanced by off sessions.
 static PassParams advance(const PassParams& p, uint64_t off) {
     PassParams q = p;
@@ -1963,8 +2068,7 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
         // Lookups that walk global memory (trie, learned windows, large binary
         // searches) run as their own barrier-free pass; stage 1 then reads the
         // labels (1 byte per session) instead of stalling its barriers on them.
-        const bool split = kind == KK_TRIE || kind == KK_PLA || kind == KK_MLP ||
-                           (kind == KK_BSEARCH && p.t.top_log2 > 0);
+        const bool split = kind != KK_LABEL_IN && lookup_splits(p.t);
         const size_t wsb = part_ws_bytes(len, p.n_bins);
         const size_t lab_bytes = split && !q.label_out ? ((len + 255) & ~(uint64_t)255) : 0;
         void* ws = nullptr;

@@ -66,6 +66,7 @@ constexpr uint32_t kPlaRadixBits = 12;          // PLA segment directory: top 12
 constexpr uint32_t kPlaWindowErr = 6;           // largest bound one 16-boundary window serves
 constexpr uint32_t kBTail = 20;                 // 0xFFFFFFFF past the padded boundaries
 constexpr uint32_t kInoutKind = 6;              // internal kind: label-only via the in/out index
+constexpr uint32_t kLabelInKind = 100;          // internal kind: stage 1 on stored labels
 __host__ __device__ constexpr uint32_t radix_words(uint32_t bits) {
     return ((1u << bits) + 2) / 2;  // (2^bits + 1) u16 entries
 }
@@ -218,6 +219,10 @@ sinet_status launch_batch_far(uint32_t kind, const BatchArgs& a, const PartWs& w
 sinet_status launch_zero_jobs(const ZeroJob* jobs, uint32_t n_jobs, hipStream_t s);
 sinet_status launch_scan_fill(const PartWs& w, hipStream_t s);
 uint32_t batch_stage1_blocks_per_cu(uint32_t kind, size_t lds);
+// lookups that run as their own pass before stage 1
+bool lookup_splits(const DevTable& t);
+sinet_status launch_batch_lookup(uint32_t kind, const BatchArgs& a, size_t lds, uint32_t grid,
+                                 hipStream_t s);
 
 // learned.hip
 sinet_status train_pla(sinet_table* t, uint32_t segments, uint32_t target_err, uint32_t max_segments,

@@ -599,6 +599,57 @@ def test_batch_equals_per_stream_and_oracle(sinet, torch):
         _cmp_hist(sinet, out, (ec, eb, ed))
 
 
+def test_batch_with_separate_lookup_pass(sinet, torch):
+    """Streams whose lookups walk global memory (trie, learned PLA and MLP,
+    in/out index off) run a batched lookup pass that stores the labels, then
+    stage 1 on stored labels: outputs equal per-stream calls and the oracle,
+    also for a stream without label output (plan-owned buffer) and one whose
+    label output is off 4-byte alignment."""
+    import sinetgen.gpu as gg
+    streams = sinetgen.batch_streams(seed=41, n_streams=6, total=1_500_000, hist_cap=2 << 30)
+    kinds = ["trie", "pla", "mlp", "pla", "trie", "bsearch"]
+    built = []
+    for k, wl in enumerate(streams):
+        cols = gg.alloc_and_fill(wl)
+        tab = sinet.Table(wl.pbase, wl.plen, kind=kinds[k], inout_index=False)
+        if kinds[k] in ("pla", "mlp"):
+            tab.train(steps=300)
+        if k == 1:
+            lab = None
+        elif k == 4:
+            lab = torch.empty(wl.n + 1, dtype=torch.uint8, device="cuda")[1:]
+        else:
+            lab = torch.empty(wl.n, dtype=torch.uint8, device="cuda")
+        out = sinet.new_hist(wl.window.n_bins)
+        built.append((wl, cols, tab, lab, out))
+    torch.cuda.synchronize()
+    plan = sinet.BatchPlan(_bstreams(sinet, built))
+    ref = [sinet.pipeline(tab, c["ts"], c["src"], c["dst"], c["bytes"], wl.window.t0,
+                          wl.window.width, wl.window.n_bins)
+           for wl, c, tab, lab, out in built]
+    for rep in range(2):
+        for _, _, _, lab, out in built:
+            if lab is not None:
+                lab.fill_(7)
+            for t in out:
+                t.fill_(-1)
+        plan.run()
+        torch.cuda.synchronize()
+        for (wl, c, tab, lab, out), (l2, o2) in zip(built, ref):
+            if lab is not None:
+                assert torch.equal(lab, l2), (rep, wl.name)
+            for x, y in zip(out, o2):
+                assert torch.equal(x, y), (rep, wl.name)
+    for wl, c, tab, lab, out in built[:3]:
+        s = sinetgen.sessions(wl)
+        w = wl.window
+        elab, ec, eb, ed = oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"], s["bytes"],
+                                           w.t0, w.width, w.n_bins)
+        if lab is not None:
+            assert np.array_equal(lab.cpu().numpy(), elab), wl.name
+        _cmp_hist(sinet, out, (ec, eb, ed))
+
+
 def test_autotune_candidates_identical(sinet, torch, tmp_path):
     built = _batch_setup(sinet, torch, n_streams=6, total=600_000)
     bs = _bstreams(sinet, built)
