@@ -1,5 +1,5 @@
 // libsinet kernels: per-session discrimination fused with the millisecond
-// histogram (one pass over the session columns), for gfx950.
+// histogram, for gfx950.
 //
 // Method (Ando et al., arXiv 2106.12863):
 //   * Algorithm 1: an address is inside a CIDR block when
@@ -9,22 +9,23 @@
 //   * Sections "Map" / "Reduce" / "Merge Scatter Pattern": every session maps
 //     to key (label, floor((ts - t0) / width)) with value (1, bytes); values
 //     merge by unsigned 64-bit addition, associative and commutative, so the
-//     order of the device-scope atomic adds below is free and the result is
-//     exact.
+//     order of accumulation is free and the result is exact.
 //
 // GPU design (what differs from the paper's Thrust transform + pairwise
 // reduction + CPU merge):
-//   * one persistent pass; each lane owns 4 consecutive sessions and reads
-//     them with 128-bit loads per column (two for the 64-bit byte column) and
-//     writes the 4 labels as one 32-bit store;
-//   * the table's hot structure (sampled boundaries, membership bits, model
-//     parameters, or the prefix rows for the scan) is staged in LDS once per
-//     workgroup;
-//   * the nearly time-sorted stream is cut into 8 contiguous index ranges,
-//     one per XCD (workgroups are dealt to XCDs round-robin), so the bins a
-//     range touches stay in that XCD's L2 while its atomics land;
-//   * the merge happens in HBM-resident u64 bins with agent-scope atomics
-//     executed in L2; no CPU stage.
+//   * stage 1 (k_stage1): each lane owns 4 consecutive sessions, read with
+//     128-bit loads per column (two for the 64-bit byte column) one chunk
+//     ahead; it classifies them against the table staged in LDS, writes the
+//     4 labels as one 32-bit store, and counting-sorts the chunk by 1,024-bin
+//     block into 4-byte records;
+//   * stage 2 (k_stage2): persistent workgroups reduce one block's records in
+//     LDS and write every bin of the block once; no zero-fill and no global
+//     atomics on the hot path; sessions outside a chunk's block window take
+//     a far pass with device-scope atomics, so any input order stays exact;
+//   * lookups that walk global memory (trie, learned windows, binary search
+//     with a global leaf) run as their own pass that stores the labels first;
+//   * the batched form runs the same stages over many streams from device
+//     work queues, captured in one graph.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
