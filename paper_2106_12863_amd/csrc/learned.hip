@@ -7,11 +7,14 @@
 // prediction bounds a search over [p - e, p + e] whose bracket is checked, so
 // lookups stay exact whatever the model's quality.
 //
-//   PLA: S equal-count segments (knot_s = B[floor(s m / S)]), each a
-//        least-squares line j ~ c_s + g_s (a - knot_s), fitted in float64 on
-//        the GPU and stored in float32 with g_s >= 0, so the float32
-//        prediction is monotone inside a segment and the error measured at
-//        both ends of every interval bounds every address.
+//   PLA: segments (knot_s, c_s, g_s) predicting j ~ c_s + g_s (a - knot_s)
+//        in float32 with g_s >= 0, so the prediction is monotone inside a
+//        segment and the error measured at both ends of every interval bounds
+//        every address.  Either an error-bounded greedy segmentation on the
+//        host (the default; it aims at a bound small enough for the window
+//        search of the lookup kernels), or S equal-count segments
+//        (knot_s = B[floor(s m / S)]) with least-squares lines fitted in
+//        float64 on the GPU.
 //   MLP: 1-16-1 ReLU network on x = a / 2^32 fitted to y = j / m by
 //        full-batch Adam with this file's forward/backward kernels; it is not
 //        monotone, so the bracket check and fallback keep lookups exact.
