@@ -144,6 +144,35 @@ def _dev_check(*ts):
             raise ValueError("device tensors must be CUDA (HIP) and contiguous")
 
 
+def _sized(t, esize: int, numel: int, name: str):
+    """A device buffer of at least numel elements of esize bytes (the kernels
+    read or write exactly that many)."""
+    if t is None:
+        return
+    _dev_check(t)
+    if t.element_size() != esize:
+        raise ValueError(f"{name}: elements of {esize} bytes expected, got {t.dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {numel} elements needed, {t.numel()} given")
+
+
+def _check_hist(out, n_bins: int):
+    if len(out) < 2:
+        raise ValueError("out: (count, bytes[, dropped]) expected")
+    _sized(out[0], 8, 4 * n_bins, "count")
+    _sized(out[1], 8, 4 * n_bins, "bytes")
+    if len(out) > 2:
+        _sized(out[2], 8, 8, "dropped")
+
+
+def _check_columns(n: int, ts=None, src=None, dst=None, nbytes=None):
+    for t, es, name in ((ts, 4, "ts"), (src, 4, "src"), (dst, 4, "dst"), (nbytes, 8, "bytes")):
+        if t is not None:
+            _sized(t, es, n, name)
+            if t.numel() != n:
+                raise ValueError(f"{name}: {t.numel()} elements, the other columns have {n}")
+
+
 class Table:
     """Device-resident prefix table (library-owned)."""
 
@@ -227,8 +256,10 @@ class Table:
     def position(self, addr, out=None):
         import torch
         _dev_check(addr)
+        _sized(addr, 4, addr.numel(), "addr")
         if out is None:
             out = torch.empty_like(addr, dtype=torch.int32)
+        _sized(out, 4, addr.numel(), "out")
         _check(_lib.sinet_table_position(self.handle, _ptr(addr), addr.shape[0], _ptr(out),
                                          _stream(addr.device)), "sinet_table_position")
         return out
@@ -260,11 +291,15 @@ def discriminate(table: Table, src, dst, label=True, src_inst=False, dst_inst=Fa
     """Labels (uint8) and optional institution ids (int32 storage of uint32)."""
     import torch
     _dev_check(src, dst)
-    n = src.shape[0]
+    n = src.numel()
+    _check_columns(n, src=src, dst=dst)
     dev = src.device
     lab = _opt_out(label, n, torch.uint8, dev)
     si = _opt_out(src_inst, n, torch.int32, dev)
     di = _opt_out(dst_inst, n, torch.int32, dev)
+    _sized(lab, 1, n, "label")
+    _sized(si, 4, n, "src_inst")
+    _sized(di, 4, n, "dst_inst")
     _check(_lib.sinet_discriminate(table.handle, _ptr(src), _ptr(dst), n, _ptr(lab), _ptr(si),
                                    _ptr(di), _stream(dev)), "sinet_discriminate")
     return lab, si, di
@@ -287,10 +322,14 @@ def _hist_struct(out):
 def histogram(ts, nbytes, label, t0: int, width: int, n_bins: int, out=None,
               accumulate: bool = False):
     _dev_check(ts, nbytes, label)
+    n = ts.numel()
+    _check_columns(n, ts=ts, nbytes=nbytes)
+    _sized(label, 1, n, "label")
     out = new_hist(n_bins, ts.device) if out is None else out
+    _check_hist(out, n_bins)
     w = Window(t0, width, n_bins)
     h = _hist_struct(out)
-    _check(_lib.sinet_histogram(_ptr(ts), _ptr(nbytes), _ptr(label), ts.shape[0], ctypes.byref(w),
+    _check(_lib.sinet_histogram(_ptr(ts), _ptr(nbytes), _ptr(label), n, ctypes.byref(w),
                                 ctypes.byref(h), int(accumulate), _stream(ts.device)),
            "sinet_histogram")
     return out
@@ -301,9 +340,12 @@ def pipeline(table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: in
     """Fused discrimination + histogram.  Returns (label or None, (count, bytes, dropped))."""
     import torch
     _dev_check(ts, src, dst, nbytes)
-    n = ts.shape[0]
+    n = ts.numel()
+    _check_columns(n, ts, src, dst, nbytes)
     lab = _opt_out(label, n, torch.uint8, ts.device)
+    _sized(lab, 1, n, "label")
     out = new_hist(n_bins, ts.device) if out is None else out
+    _check_hist(out, n_bins)
     c = Columns(_ptr(ts), _ptr(src), _ptr(dst), _ptr(nbytes), n)
     w = Window(t0, width, n_bins)
     h = _hist_struct(out)
@@ -317,6 +359,9 @@ def mlp_loss_grad(params, x, y):
     """(loss[1], grad[49]) float32 device tensors."""
     import torch
     _dev_check(params, x, y)
+    _sized(params, 4, MLP_PARAMS, "params")
+    if x.element_size() != 4 or y.element_size() != 4 or y.numel() != x.numel():
+        raise ValueError("x and y: float32 of the same length expected")
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
     grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
     _check(_lib.sinet_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(y), x.shape[0], _ptr(loss),
@@ -328,6 +373,13 @@ class BatchStream:
     """One stream of a batch: columns, table, window, outputs (device tensors)."""
 
     def __init__(self, table: Table, ts, src, dst, nbytes, t0, width, n_bins, label=None, out=None):
+        _dev_check(ts, src, dst, nbytes, label)
+        n = ts.numel()
+        _check_columns(n, ts, src, dst, nbytes)
+        _sized(label, 1, n, "label")
+        if out is None:
+            raise ValueError("out: a (count, bytes[, dropped]) histogram is required")
+        _check_hist(out, n_bins)
         self.table, self.ts, self.src, self.dst, self.nbytes = table, ts, src, dst, nbytes
         self.t0, self.width, self.n_bins = t0, width, n_bins
         self.label = label

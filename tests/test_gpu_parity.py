@@ -348,6 +348,23 @@ def test_unsupported_and_bad_calls_raise(sinet, torch):
     tab2 = sinet.Table(b, l, kind="bsearch")
     with pytest.raises(sinet.SinetError):
         sinet.pipeline(tab2, x, x, x, x.long(), 0, 0, 10)   # width 0
+    # sizes the kernels would read or write past: refused before any launch
+    short = torch.zeros(7, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        sinet.pipeline(tab2, x, short, x, x.long(), 0, 1, 10)
+    with pytest.raises(ValueError):
+        sinet.pipeline(tab2, x, x, x, x, 0, 1, 10)         # 4-byte byte counts
+    with pytest.raises(ValueError):
+        sinet.pipeline(tab2, x, x, x, x.long(), 0, 1, 10, out=sinet.new_hist(9))
+    with pytest.raises(ValueError):
+        sinet.pipeline(tab2, x, x, x, x.long(), 0, 1, 10,
+                       label=torch.zeros(7, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        sinet.discriminate(tab2, x, short)
+    with pytest.raises(ValueError):
+        sinet.histogram(x, x.long(), short.to(torch.uint8), 0, 1, 10)
+    with pytest.raises(ValueError):
+        sinet.BatchStream(tab2, x, x, x, x.long(), 0, 1, 10, out=sinet.new_hist(5))
 
 
 # ------------------------------------------------------ intervals/positions
