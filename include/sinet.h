@@ -266,9 +266,17 @@ sinet_status sinet_mlp_loss_grad(const float* params, const float* x, const floa
 sinet_status sinet_autotune(const sinet_stream* streams, uint32_t n_streams,
                             const char* cache_path, hipStream_t stream, sinet_tune* out);
 
-/* Prepare a batch: stream descriptors uploaded, clear + one persistent
- * work-queue launch captured in a hipGraph.  tune may be NULL (defaults).
- * The plan refers to the caller's buffers, which must outlive it. */
+/* Prepare a batch (sections "Coordinated Batch Processing", "Work Queue"):
+ * stream descriptors uploaded, and the clears, one persistent work-queue
+ * launch per lookup kind, the shared segment index, the block reduction and
+ * the far pass captured in one hipGraph.  Streams whose lookups walk device
+ * memory (trie, learned, sampled binary search; see sinet_table_create) get a
+ * batched lookup pass that stores their labels first, into the stream's label
+ * output or, when it has none, a buffer of n bytes held by the plan.  tune may
+ * be NULL (defaults).  The plan refers to the caller's buffers and tables,
+ * which must outlive it.  Errors: INVALID_ARG (no streams, NULL column or
+ * histogram, untrained learned table, bad window), UNSUPPORTED (more than
+ * 2^32 record slots in one plan), OUT_OF_MEMORY.  Synchronous. */
 sinet_status sinet_batch_plan_create(const sinet_stream* streams, uint32_t n_streams,
                                      const sinet_tune* tune, hipStream_t stream,
                                      sinet_batch_plan** out);
