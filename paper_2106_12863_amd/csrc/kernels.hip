@@ -916,6 +916,7 @@ __global__ void __launch_bounds__(kStage1Block, 4) k_stage1(PassParams p, PartWs
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ Stage1Shared sh[2];
     __shared__ uint4 srec[kChunkSlots / 4];
+    __shared__ uint32_t s_run;
     uint32_t used = 0;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
     Dropped d{};
@@ -924,14 +925,23 @@ __global__ void __launch_bounds__(kStage1Block, 4) k_stage1(PassParams p, PartWs
     uint32_t iter = 0;
     // a chunk is "full" when its kChunk sessions exist and vector loads are allowed
     auto full = [&](uint64_t c) { return w.vec && (c + 1) * kChunk <= p.n; };
-    Raw4 cur{}, nxt{};
-    uint64_t c = blockIdx.x;
-    if (c < n_chunks && full(c)) load4<KIND>(p, c * kChunk + (uint64_t)tid * 4, cur);
-    for (; c < n_chunks; c += gridDim.x) {
-        const uint64_t cn = c + gridDim.x;
-        if (cn < n_chunks && full(cn)) load4<KIND>(p, cn * kChunk + (uint64_t)tid * 4, nxt);
-        stage1_chunk<KIND>(p, w, v, sh[iter++ & 1u], srec, c, c, 0u, cur, full(c), d);
-        cur = nxt;
+    // workgroups take runs of kStage1Run consecutive chunks from a counter, so
+    // one that falls behind (a busy XCD, a chunk of far sessions) takes fewer;
+    // every lane reads s_run before the chunk's first barrier, tid 0 writes it
+    // again only after the run's last one
+    for (;;) {
+        if (tid == 0) s_run = atomicAdd(w.next_run, 1u);
+        __syncthreads();
+        const uint64_t c0 = (uint64_t)__builtin_amdgcn_readfirstlane((int)s_run) * kStage1Run;
+        if (c0 >= n_chunks) break;
+        const uint64_t c1 = c0 + kStage1Run < n_chunks ? c0 + kStage1Run : n_chunks;
+        Raw4 cur{}, nxt{};
+        if (full(c0)) load4<KIND>(p, c0 * kChunk + (uint64_t)tid * 4, cur);
+        for (uint64_t c = c0; c < c1; ++c) {
+            if (c + 1 < c1 && full(c + 1)) load4<KIND>(p, (c + 1) * kChunk + (uint64_t)tid * 4, nxt);
+            stage1_chunk<KIND>(p, w, v, sh[iter++ & 1u], srec, c, c, 0u, cur, full(c), d);
+            cur = nxt;
+        }
     }
     d.flush(p.dropped);
 }
@@ -1703,6 +1713,7 @@ PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins) {
     w.segs = (uint2*)take(8 * nc * kWin);
     w.scan_tiles = (uint32_t*)take(4 * nt);
     w.farcount = (uint32_t*)take(256);
+    w.next_run = w.farcount + 1;
     w.n_chunks = nc;
     w.n_blocks = (uint32_t)nb;
     return w;
@@ -1820,7 +1831,7 @@ sinet_status run_partitioned(const PassParams& p0, uint32_t kind, const PartWs& 
     PartWs wv = w;
     wv.vec = vec ? 1u : 0u;
     sinet_status st = launch_zero32(w.seg_count, w.n_blocks, s);
-    if (st == SINET_OK) st = launch_zero32(w.farcount, 1, s);
+    if (st == SINET_OK) st = launch_zero32(w.farcount, 2, s);  // far count, run counter
     if (st != SINET_OK) return st;
     Stage1Fn f1 = pick_stage1(kind);
     const size_t lds = (kind == KK_LABEL_IN ? 0 : p.t.lds_bytes) + 8;

@@ -79,6 +79,7 @@ constexpr int kExtraRecs = 384;     // records beyond one per session a chunk ma
 // record slots of a chunk: one per session, the extra part records of large byte
 // counts, and the padding of every block's segment to whole 16-byte groups
 constexpr int kChunkSlots = kChunk + kExtraRecs + 3 * kWin;
+constexpr int kStage1Run = 4;       // chunks a stage-1 workgroup takes at a time
 constexpr int kStage1Block = kChunk / 4;  // stage-1 lanes: 4 sessions each
 
 // Device workspace of the partitioned histogram (carved from one allocation).
@@ -89,6 +90,7 @@ struct PartWs {
     uint32_t* farbits;              // [n_chunks * kChunk / 32] far sessions (flagged chunks)
     uint32_t* farlist;              // [n_chunks] chunks holding far sessions
     uint32_t* farcount;             // [1]
+    uint32_t* next_run;             // [1] next run of kStage1Run chunks to take (k_stage1)
     uint32_t* seg_count;            // [n_blocks] directory entries per block
     uint32_t* seg_off;              // [n_blocks + 1] exclusive scan of seg_count
     uint2* segs;                    // [n_chunks * kWin] (first slot, slots) grouped by block
