@@ -1116,63 +1116,82 @@ __device__ __forceinline__ void store_pair(unsigned long long* q, unsigned long 
     __builtin_nontemporal_store(u64x2_t{x, y}, glob(reinterpret_cast<u64x2_t*>(q)));
 }
 
-// Write the block's bins (two consecutive bins per lane, 16-byte stores when
-// the label rows are 16-byte aligned, which holds when n_bins is even) and
-// clear the accumulators it read.  A block without records (empty) writes
-// zeros without touching the accumulators, which are already clear.
+// Bins from an output row's start to its first 128-byte line boundary.  Blocks
+// start at multiples of kBlockBins bins (8 KB), so a row's skew is the same in
+// every block.
+__device__ __forceinline__ uint32_t line_skew(const unsigned long long* row) {
+    return (uint32_t)(((128u - ((uintptr_t)row & 127u)) & 127u) >> 3);
+}
+
+// Write the block's bins and clear the accumulators it read.  Two consecutive
+// bins per lane with 16-byte stores when the label rows are 16-byte aligned
+// (n_bins even), else one.  Within every row the lanes start at the row's
+// first 128-byte line boundary inside the block and wrap around to the bins
+// before it, so each wave store covers whole lines and only the two lines a
+// block shares with its neighbours are written in part.  On rows that are not
+// line-aligned (n_bins * 8 not a multiple of 128, or an offset buffer) wave
+// stores that straddle lines cost about a fifth of the write rate.  A block
+// without records (empty) writes zeros without touching the accumulators,
+// which are already clear.
 __device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t, bool empty) {
     const uint64_t b0 = (uint64_t)t.blk * kBlockBins;
     const bool pairs =
         (t.n_bins & 1u) == 0 && (((uintptr_t)t.count | (uintptr_t)t.hbytes) & 15u) == 0;
-    if (pairs && empty && !t.accumulate) {
+    if (pairs) {
+        const bool zeros = empty && !t.accumulate;
         for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
-            const uint32_t e = 2 * k;
-            const uint32_t lab = e / kBlockBins, off = e % kBlockBins;
-            const uint64_t bin = b0 + off;
-            if (bin >= t.n_bins) continue;
-            const uint64_t o = (uint64_t)lab * t.n_bins + bin;
-            store_pair(t.count + o, 0ull, 0ull);
-            store_pair(t.hbytes + o, 0ull, 0ull);
-        }
-    } else if (pairs) {
-        for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
-            const uint32_t e = 2 * k;
-            const uint32_t lab = e / kBlockBins, off = e % kBlockBins;
-            const uint64_t bin = b0 + off;
-            ulonglong2 c = make_ulonglong2(sh.c[e], sh.c[e + 1]);
-            ulonglong2 b = make_ulonglong2(sh.b[e], sh.b[e + 1]);
-            sh.c[e] = 0;
-            sh.c[e + 1] = 0;
-            sh.b[e] = 0;
-            sh.b[e + 1] = 0;
-            if (bin >= t.n_bins) continue;  // n_bins even: bin + 1 is inside too
-            const uint64_t o = (uint64_t)lab * t.n_bins + bin;
-            if (t.accumulate) {
-                const ulonglong2 oc = *reinterpret_cast<const ulonglong2*>(t.count + o);
-                const ulonglong2 ob = *reinterpret_cast<const ulonglong2*>(t.hbytes + o);
-                c.x += oc.x;
-                c.y += oc.y;
-                b.x += ob.x;
-                b.y += ob.y;
+            const uint32_t lab = k / (kBlockBins / 2), j = k % (kBlockBins / 2);
+            const uint64_t row = (uint64_t)lab * t.n_bins;
+            // skews are even here: the rows are 16-byte aligned
+            const uint32_t oc = (line_skew(t.count + row) + 2 * j) & (kBlockBins - 1);
+            const uint32_t ob = (line_skew(t.hbytes + row) + 2 * j) & (kBlockBins - 1);
+            const uint32_t ec = lab * kBlockBins + oc, eb = lab * kBlockBins + ob;
+            ulonglong2 c = make_ulonglong2(0ull, 0ull), b = make_ulonglong2(0ull, 0ull);
+            if (!zeros) {
+                c = make_ulonglong2(sh.c[ec], sh.c[ec + 1]);
+                b = make_ulonglong2(sh.b[eb], sh.b[eb + 1]);
+                sh.c[ec] = 0;
+                sh.c[ec + 1] = 0;
+                sh.b[eb] = 0;
+                sh.b[eb + 1] = 0;
             }
-            store_pair(t.count + o, c.x, c.y);
-            store_pair(t.hbytes + o, b.x, b.y);
+            // n_bins even: bin + 1 is inside whenever bin is
+            if (b0 + oc < t.n_bins) {
+                unsigned long long* q = t.count + row + b0 + oc;
+                if (t.accumulate) {
+                    const ulonglong2 o = *reinterpret_cast<const ulonglong2*>(q);
+                    c.x += o.x;
+                    c.y += o.y;
+                }
+                store_pair(q, c.x, c.y);
+            }
+            if (b0 + ob < t.n_bins) {
+                unsigned long long* q = t.hbytes + row + b0 + ob;
+                if (t.accumulate) {
+                    const ulonglong2 o = *reinterpret_cast<const ulonglong2*>(q);
+                    b.x += o.x;
+                    b.y += o.y;
+                }
+                store_pair(q, b.x, b.y);
+            }
         }
     } else {
         for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
-            const uint32_t lab = k / kBlockBins, off = k % kBlockBins;
-            const uint64_t bin = b0 + off;
-            unsigned long long c = sh.c[k], b = sh.b[k];
-            sh.c[k] = 0;
-            sh.b[k] = 0;
-            if (bin >= t.n_bins) continue;
-            const uint64_t o = (uint64_t)lab * t.n_bins + bin;
-            if (t.accumulate) {
-                c += t.count[o];
-                b += t.hbytes[o];
+            const uint32_t lab = k / kBlockBins, j = k % kBlockBins;
+            const uint64_t row = (uint64_t)lab * t.n_bins;
+            const uint32_t oc = (line_skew(t.count + row) + j) & (kBlockBins - 1);
+            const uint32_t ob = (line_skew(t.hbytes + row) + j) & (kBlockBins - 1);
+            unsigned long long c = sh.c[lab * kBlockBins + oc], b = sh.b[lab * kBlockBins + ob];
+            sh.c[lab * kBlockBins + oc] = 0;
+            sh.b[lab * kBlockBins + ob] = 0;
+            if (b0 + oc < t.n_bins) {
+                unsigned long long* q = t.count + row + b0 + oc;
+                *q = t.accumulate ? *q + c : c;
             }
-            t.count[o] = c;
-            t.hbytes[o] = b;
+            if (b0 + ob < t.n_bins) {
+                unsigned long long* q = t.hbytes + row + b0 + ob;
+                *q = t.accumulate ? *q + b : b;
+            }
         }
     }
 }

@@ -199,6 +199,44 @@ def test_histogram_entry_and_accumulate(sinet, torch):
     _cmp_hist(sinet, acc, exp)
 
 
+@pytest.mark.parametrize("n_bins,co,bo", [(5_122, 0, 2), (5_122, 6, 14), (4_104, 4, 10),
+                                          (3_073, 0, 1), (5_122, 9, 3)])
+def test_histogram_rows_off_line_boundaries(sinet, torch, n_bins, co, bo):
+    """Output rows that start anywhere relative to 128-byte lines (the row
+    stride n_bins * 8 and the buffers' own offsets), with 16- and 8-byte
+    stores: every bin is written once, nothing outside the rows is touched."""
+    wl = sinetgen.config(1, n=300_007)
+    _say("histogram rows", n_bins, co, bo)
+    s = sinetgen.sessions(wl)
+    lab = oracle.classify(wl.pbase, wl.plen, s["src"], s["dst"], want_inst=False)
+    ts, _, _, nb = _up(sinet, s)
+    lt = torch.from_numpy(lab).cuda()
+    t0, w = 100, 1
+    exp = oracle.histogram(s["ts"], s["bytes"], lab, t0, w, n_bins)
+    guard = -7
+    bc = torch.full((co + 4 * n_bins + 5,), guard, dtype=torch.int64, device="cuda")
+    bb = torch.full((bo + 4 * n_bins + 5,), guard, dtype=torch.int64, device="cuda")
+    out = (bc[co:co + 4 * n_bins].view(4, n_bins), bb[bo:bo + 4 * n_bins].view(4, n_bins),
+           torch.empty((4, 2), dtype=torch.int64, device="cuda"))
+    sinet.histogram(ts, nb, lt, t0, w, n_bins, out=out)
+    torch.cuda.synchronize()
+    _cmp_hist(sinet, out, exp)
+    # accumulate onto earlier contents
+    base_c = torch.arange(4 * n_bins, dtype=torch.int64, device="cuda").view(4, n_bins) * 3
+    base_b = torch.arange(4 * n_bins, dtype=torch.int64, device="cuda").view(4, n_bins) * 5 + 11
+    out[0].copy_(base_c)
+    out[1].copy_(base_b)
+    out[2].zero_()
+    sinet.histogram(ts, nb, lt, t0, w, n_bins, out=out, accumulate=True)
+    torch.cuda.synchronize()
+    ec, eb, ed = exp
+    _cmp_hist(sinet, out, (ec + sinet.to_host_u64(base_c), eb + sinet.to_host_u64(base_b), ed))
+    for buf, off in ((bc, co), (bb, bo)):
+        h = buf.cpu().numpy()
+        assert (h[:off] == guard).all() and (h[off + 4 * n_bins:] == guard).all(), \
+            "a write outside the histogram rows"
+
+
 def test_pipeline_chunked_accumulate_equals_whole(sinet, torch):
     wl = sinetgen.config(2, n=1_000_000)
     _say("chunked accumulate")
