@@ -56,6 +56,9 @@ def lib():
         L.or_pipeline.argtypes = [P, P, P, u64, i32, P, P, P, P, u64, u32, u32, u32,
                                   P, P, P, P, i32]
         L.or_pipeline.restype = i32
+        L.or_watch.argtypes = [P, P, P, u64, i32, P, P, P, P, u64, u32, u32, u32, u32,
+                               P, P, P, i32]
+        L.or_watch.restype = i32
         L.or_endpoints.argtypes = [P, P, u64, P, P]
         L.or_endpoints.restype = ctypes.c_int64
         _lib = L
@@ -145,6 +148,34 @@ def pipeline(base, plen, ts, src, dst, nbytes, t0, width, n_bins, inst=None,
                            n, t0, width, n_bins, _p(label), _p(cnt), _p(byt), _p(drp), 0)
     assert rc == 0
     return label, cnt, byt, drp
+
+
+def watch(base, plen, ts, src, dst, nbytes, t0, width, n_bins, n_keys, inst=None,
+          mode: str = "hash", out=None):
+    """Watch-list histograms: (count[2, n_keys, n_bins], bytes[2, n_keys,
+    n_bins], dropped[2, 2]) as uint64.  Direction 0 counts sessions whose
+    source matches the list (key of its longest match), direction 1 those
+    whose destination does.  With ``out`` given, adds into it."""
+    base, plen, inst = _table(base, plen, inst)
+    ts = np.ascontiguousarray(ts, dtype=np.uint32)
+    src = np.ascontiguousarray(src, dtype=np.uint32)
+    dst = np.ascontiguousarray(dst, dtype=np.uint32)
+    nbytes = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    if out is None:
+        cnt = np.empty((2, n_keys, n_bins), np.uint64)
+        byt = np.empty((2, n_keys, n_bins), np.uint64)
+        drp = np.empty((2, 2), np.uint64)
+        acc = 0
+    else:
+        cnt, byt, drp = out
+        acc = 1
+    rc = lib().or_watch(_p(base), _p(plen), _p(inst), base.shape[0],
+                        0 if mode == "scan" else 1, _p(ts), _p(src), _p(dst), _p(nbytes),
+                        ts.shape[0], t0, width, n_bins, n_keys, _p(cnt), _p(byt), _p(drp), acc)
+    if rc == 2:
+        raise ValueError("a key is not below n_keys")
+    assert rc == 0
+    return cnt, byt, drp
 
 
 def endpoints(base, plen):

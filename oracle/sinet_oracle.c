@@ -210,6 +210,64 @@ int or_pipeline(const uint32_t* base, const uint8_t* len, const uint32_t* inst,
 }
 
 /* ------------------------------------------------------------------------
+ * Watch-list histograms (section "AbuseIPDB", section "GRIZZLY STEPPE",
+ * Figures 8-11): the sessions that involve a listed host, counted per time
+ * window and per direction.  The list is a prefix table (usually /32 hosts);
+ * each row carries a key (inst: one key per host, or one per list), and the
+ * longest match decides an address's key, as for institutions.
+ *   direction 0 (SRC): the source matches the list, key = key(lpm(src));
+ *                      for lists of outside hosts, the list's ingoing sessions;
+ *   direction 1 (DST): the destination matches, key = key(lpm(dst));
+ *                      the list's outgoing sessions.
+ * A session whose two endpoints both match counts once in each direction.
+ * count/bytes are [2][n_keys][n_bins] (direction-major, then key), dropped
+ * is [2][2] = {count, bytes} per direction for matched sessions outside the
+ * window.  Keys must be < n_keys (else the call fails with 2).  With
+ * accumulate == 0 the outputs are cleared first.
+ * ---------------------------------------------------------------------- */
+int or_watch(const uint32_t* base, const uint8_t* len, const uint32_t* inst,
+             uint64_t n_prefix, int mode, const uint32_t* ts, const uint32_t* src,
+             const uint32_t* dst, const uint64_t* bytes, uint64_t n, uint32_t t0,
+             uint32_t width, uint32_t n_bins, uint32_t n_keys, uint64_t* count,
+             uint64_t* bytesh, uint64_t* dropped, int accumulate) {
+    if (width == 0 || n_bins == 0 || n_keys == 0) return 1;
+    for (uint64_t p = 0; p < n_prefix; ++p)
+        if ((inst ? inst[p] : (uint32_t)p) >= n_keys) return 2;
+    const uint64_t cells = 2ull * n_keys * n_bins;
+    if (!accumulate) {
+        memset(count, 0, sizeof(uint64_t) * cells);
+        memset(bytesh, 0, sizeof(uint64_t) * cells);
+        if (dropped) memset(dropped, 0, sizeof(uint64_t) * 4);
+    }
+    or_index* ix = NULL;
+    if (mode == 1) {
+        ix = or_index_build(base, len, n_prefix);
+        if (!ix) return 1;
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t ends[2] = {src[i], dst[i]};
+        for (int dir = 0; dir < 2; ++dir) {
+            int64_t row;
+            int hit = mode ? or_index_lookup(ix, ends[dir], &row)
+                           : or_lookup_scan(base, len, n_prefix, ends[dir], &row);
+            if (!hit) continue;
+            uint64_t key = inst ? inst[row] : (uint64_t)row;
+            if (ts[i] >= t0 && (ts[i] - t0) / width < n_bins) {
+                uint64_t b = (ts[i] - t0) / width;
+                uint64_t c = ((uint64_t)dir * n_keys + key) * n_bins + b;
+                count[c] += 1;
+                bytesh[c] += bytes[i];
+            } else if (dropped) {
+                dropped[dir * 2 + 0] += 1;
+                dropped[dir * 2 + 1] += bytes[i];
+            }
+        }
+    }
+    or_index_free(ix);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Elementary intervals of a prefix table (used to state what a position
  * search over sorted boundaries must return).  Every prefix p covers
  * [bitmask(base_p, Z_p), that + 2^(32-Z_p)); the sorted distinct starts and

@@ -43,6 +43,7 @@ LTAB_K = 65536          # knots of the lognormal quantile table
 
 # column stream ids (one independent SplitMix64 stream each)
 COL_TS, COL_SRC, COL_SRCP, COL_DST, COL_DSTP, COL_BYTES = 1, 2, 3, 4, 5, 6
+COL_WSRC, COL_WDST = 7, 8   # watch-list overlay of sources / destinations
 
 TS_UNIFORM, TS_DIURNAL, TS_STRATIFIED = 0, 1, 2
 
@@ -247,20 +248,88 @@ def _bytes(wl: Workload, idx: np.ndarray) -> np.ndarray:
     return lo + ((d * f) >> U64(16))
 
 
-def sessions(wl: Workload, idx=None, start: int = 0, stop: Optional[int] = None):
+def sessions(wl: Workload, idx=None, start: int = 0, stop: Optional[int] = None,
+             watch: Optional["WatchList"] = None):
     """Columns ts/src/dst (uint32) and bytes (uint64) for the given indices
-    (or the range [start, stop))."""
+    (or the range [start, stop)); with ``watch``, the list's hosts are
+    placed in (``watch_overlay``)."""
     if idx is None:
         stop = wl.n if stop is None else stop
         idx = np.arange(start, stop, dtype=np.int64)
     idx = np.asarray(idx, dtype=np.int64)
     k = wl.keys()
+    src = _addr(wl, idx, k[1], k[2])
+    dst = _addr(wl, idx, k[3], k[4])
+    if watch is not None:
+        src, dst = watch_overlay(watch, idx, src, dst)
     return {
         "ts": _ts(wl, idx),
-        "src": _addr(wl, idx, k[1], k[2]),
-        "dst": _addr(wl, idx, k[3], k[4]),
+        "src": src,
+        "dst": dst,
         "bytes": _bytes(wl, idx),
     }
+
+
+# ----------------------------------------------------------------------------
+# Watch lists (sections "AbuseIPDB" and "GRIZZLY STEPPE": per-host session
+# counts of published lists of malicious addresses)
+# ----------------------------------------------------------------------------
+@dataclass
+class WatchList:
+    """Listed hosts and how often sessions involve them.
+
+    addrs: distinct /32 host addresses; lists: the list each host belongs to.
+    With ``watch_overlay``, a share ``frac`` of the sessions has its source
+    replaced by a listed host, and independently a share ``frac`` its
+    destination; the host is drawn as floor(K * u^2) for u uniform in [0, 1),
+    so a few hosts carry most of the listed sessions."""
+    name: str
+    addrs: np.ndarray
+    lists: np.ndarray
+    seed: int
+    frac: float = 0.002
+
+    @property
+    def n(self) -> int:
+        return int(self.addrs.shape[0])
+
+    @property
+    def thr(self) -> int:
+        return min(int(self.frac * 2.0 ** 32), 2 ** 32 - 1)
+
+    def keys(self):
+        return stream_key(self.seed, COL_WSRC), stream_key(self.seed, COL_WDST)
+
+
+def watch_lists(seed: int = 6, sizes=(300, 877), frac: float = 0.002) -> WatchList:
+    """Two synthetic lists of distinct random /32 hosts, sized like the
+    paper's AbuseIPDB sample (300 addresses) and the GRIZZLY STEPPE report
+    (877 addresses).  The real lists are not used."""
+    rng = np.random.Generator(np.random.PCG64(seed * 7919 + 6))
+    need = int(sum(sizes))
+    seen, addrs = set(), []
+    while len(addrs) < need:
+        a = int(rng.integers(0, 1 << 32))
+        if a not in seen:
+            seen.add(a)
+            addrs.append(a)
+    lists = np.concatenate([np.full(k, j, np.uint32) for j, k in enumerate(sizes)])
+    return WatchList(f"watch-{'+'.join(str(k) for k in sizes)}hosts", np.asarray(addrs, np.uint32),
+                     lists, seed, frac)
+
+
+def watch_overlay(wlist: WatchList, idx: np.ndarray, src: np.ndarray, dst: np.ndarray):
+    """Sources and destinations of sessions ``idx`` with the list's hosts
+    placed in (new arrays)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    out = []
+    for key, col in zip(wlist.keys(), (src, dst)):
+        r = draw(key, idx)
+        hit = (r & U64(0xFFFFFFFF)) < U64(wlist.thr)
+        u = r >> U64(32)
+        pick = _mulhi32((u * u) >> U64(32), wlist.n).astype(np.int64)
+        out.append(np.where(hit, wlist.addrs[pick], np.asarray(col, np.uint32)).astype(np.uint32))
+    return out[0], out[1]
 
 
 # ----------------------------------------------------------------------------

@@ -102,7 +102,40 @@ __global__ void k_gen(sinetgen_params p, const uint32_t* __restrict__ pbase,
     }
 }
 
+// Watch-list overlay: sessions i0 + j whose draw from the source (or
+// destination) overlay stream falls below thr get a listed host, picked as
+// floor(K * u^2) with u the draw's high word over 2^32.
+__global__ void k_watch(const uint32_t* __restrict__ addrs, uint32_t K, uint64_t key_src,
+                        uint64_t key_dst, uint32_t thr, uint64_t i0, uint64_t n,
+                        uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        uint64_t i = i0 + j;
+        uint64_t rs = draw(key_src, i), rd = draw(key_dst, i);
+        if ((rs & 0xFFFFFFFFull) < thr) {
+            uint64_t u = rs >> 32;
+            src[j] = addrs[mulhi32((u * u) >> 32, K)];
+        }
+        if ((rd & 0xFFFFFFFFull) < thr) {
+            uint64_t u = rd >> 32;
+            dst[j] = addrs[mulhi32((u * u) >> 32, K)];
+        }
+    }
+}
+
 }  // namespace
+
+extern "C" int sinetgen_watch(const uint32_t* addrs, uint32_t K, uint64_t key_src,
+                              uint64_t key_dst, uint32_t thr, uint64_t i0, uint64_t n,
+                              uint32_t* src, uint32_t* dst, hipStream_t stream) {
+    if (!addrs || K == 0 || !src || !dst) return 1;
+    if (n == 0) return 0;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_watch, dim3((unsigned)blocks), dim3(256), 0, stream, addrs, K, key_src,
+                       key_dst, thr, i0, n, src, dst);
+    return hipGetLastError() == hipSuccess ? 0 : 2;
+}
 
 extern "C" int sinetgen_fill(const sinetgen_params* p, const uint32_t* pbase,
                              const uint8_t* plen, const uint64_t* qtab,

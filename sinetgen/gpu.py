@@ -50,6 +50,11 @@ def _load():
         _lib.sinetgen_fill.argtypes = [ctypes.POINTER(_Params)] + [ctypes.c_void_p] * 4 + [
             ctypes.c_uint64, ctypes.c_uint64] + [ctypes.c_void_p] * 5
         _lib.sinetgen_fill.restype = ctypes.c_int
+        _lib.sinetgen_watch.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        _lib.sinetgen_watch.restype = ctypes.c_int
     return _lib
 
 
@@ -86,6 +91,23 @@ def fill(wl: Workload, ts=None, src=None, dst=None, nbytes=None, i0: int = 0, n=
                            ptr(ts), ptr(src), ptr(dst), ptr(nbytes), ctypes.c_void_p(stream))
     if rc != 0:
         raise RuntimeError(f"sinetgen_fill failed ({rc})")
+
+
+def watch_fill(wlist, src, dst, i0: int = 0):
+    """Place the list's hosts into device columns holding sessions
+    [i0, i0 + len) (the same values as ``sinetgen.watch_overlay``)."""
+    import torch
+    lib = _load()
+    n = src.shape[0]
+    addrs = torch.from_numpy(wlist.addrs.view(np.int32)).to(src.device)
+    ks, kd = wlist.keys()
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    rc = lib.sinetgen_watch(ctypes.c_void_p(addrs.data_ptr()), wlist.n, ks, kd, wlist.thr, i0, n,
+                            ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                            ctypes.c_void_p(stream))
+    if rc != 0:
+        raise RuntimeError(f"sinetgen_watch failed ({rc})")
+    torch.cuda.current_stream(src.device).synchronize()  # addrs is freed on return
 
 
 def alloc_and_fill(wl: Workload, device="cuda", columns=("ts", "src", "dst", "bytes")):
