@@ -45,9 +45,9 @@ DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched,batched_pla"
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
 COUNTER_TRAFFIC = {
-    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "c0e5c335070db8c1",
+    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "061c96277ad7c13c",
                  "bytes": 40.32e9},
-    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "c0e5c335070db8c1",
+    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "061c96277ad7c13c",
                  "bytes": 12.98e9},
 }
 KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")

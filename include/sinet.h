@@ -114,6 +114,22 @@ typedef struct {
     uint64_t* dropped;
 } sinet_hist;
 
+/* Watch-list histogram outputs (device): count[2][n_keys][n_bins] and
+ * bytes[2][n_keys][n_bins], direction-major, then key, then bin; unsigned
+ * 64-bit, exact modulo 2^64.  dropped[2][2] = {count, bytes} of the matched
+ * sessions outside the window per direction, or NULL. */
+typedef enum {
+    SINET_WATCH_SRC = 0,    /* the source matched the list: for a list of outside
+                               hosts, sessions coming in from them            */
+    SINET_WATCH_DST = 1     /* the destination matched: sessions going out to them */
+} sinet_watch_dir;
+
+typedef struct {
+    uint64_t* count;
+    uint64_t* bytes;
+    uint64_t* dropped;
+} sinet_watch_hist;
+
 typedef struct {
     uint32_t kind;          /* sinet_lookup of the table                     */
     uint32_t inout_index;   /* 1: label-only queries use the in/out index    */
@@ -252,6 +268,26 @@ sinet_status sinet_histogram(const uint32_t* ts, const uint64_t* bytes, const ui
 sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols,
                             const sinet_window* win, uint8_t* label, sinet_hist* out,
                             int accumulate, hipStream_t stream);
+
+/* Watch-list histograms (sections "AbuseIPDB" and "GRIZZLY STEPPE",
+ * Figures 8-11: the sessions of the hosts on a published list per time
+ * window, ingoing and outgoing).  list is a prefix table of the listed hosts
+ * (usually /32 rows) whose inst ids are the keys: one key per host (the row
+ * index, inst == NULL at creation) or one per list.  Each session looks up
+ * its source and its destination in the list; the longest match, lowest row
+ * on equal length, gives the key.  A matched source adds (1, bytes) to
+ * count/bytes[SINET_WATCH_SRC][key][bin], a matched destination to
+ * [SINET_WATCH_DST][key][bin], with bin = floor((ts - t0_ms) / width_ms);
+ * a session whose two ends match counts once in each direction; matched
+ * sessions outside the window go to dropped[dir].  accumulate == 0: outputs
+ * cleared first; 1: added to.  Every inst id of list must be below n_keys.
+ * The list's kind may be SCAN, BSEARCH, TRIE or a trained learned kind.
+ * Errors: INVALID_ARG (NULL table, column or output, width_ms == 0,
+ * n_bins == 0, n_keys == 0, an inst id >= n_keys, 2 * n_keys * n_bins
+ * above 2^40), UNSUPPORTED (table too large for LDS).  Asynchronous. */
+sinet_status sinet_watch_histogram(const sinet_table* list, const sinet_columns* cols,
+                                   const sinet_window* win, uint32_t n_keys,
+                                   sinet_watch_hist* out, int accumulate, hipStream_t stream);
 
 /* Forward and backward of the 1-16-1 MLP position model (device arrays):
  * params[49] (w1[16], b1[16], w2[16], b2), inputs x[n], targets y[n];

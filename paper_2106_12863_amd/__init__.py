@@ -100,6 +100,8 @@ _sig("sinet_discriminate", [P, P, P, U64, P, P, P, P])
 _sig("sinet_histogram", [P, P, P, U64, ctypes.POINTER(Window), ctypes.POINTER(Hist), I32, P])
 _sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                         ctypes.POINTER(Hist), I32, P])
+_sig("sinet_watch_histogram", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), U32,
+                               ctypes.POINTER(Hist), I32, P])
 _sig("sinet_mlp_loss_grad", [P, P, P, U64, P, P, P])
 _sig("sinet_autotune", [P, U32, ctypes.c_char_p, P, ctypes.POINTER(Tune)])
 _sig("sinet_batch_plan_create", [P, U32, ctypes.POINTER(Tune), P, ctypes.POINTER(P)])
@@ -353,6 +355,41 @@ def pipeline(table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: in
                                ctypes.byref(h), int(accumulate), _stream(ts.device)),
            "sinet_pipeline")
     return lab, out
+
+
+WATCH_SRC, WATCH_DST = 0, 1
+
+
+def new_watch_hist(n_keys: int, n_bins: int, device="cuda"):
+    import torch
+    return (torch.empty((2, n_keys, n_bins), dtype=torch.int64, device=device),
+            torch.empty((2, n_keys, n_bins), dtype=torch.int64, device=device),
+            torch.empty((2, 2), dtype=torch.int64, device=device))
+
+
+def watch_histogram(wlist: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: int,
+                    n_keys: int, out=None, accumulate: bool = False):
+    """Watch-list histograms: (count[2, n_keys, n_bins], bytes[2, n_keys, n_bins],
+    dropped[2, 2]); direction WATCH_SRC counts sessions whose source matches
+    the list, WATCH_DST those whose destination does, keyed by the list
+    table's inst ids."""
+    _dev_check(ts, src, dst, nbytes)
+    n = ts.numel()
+    _check_columns(n, ts, src, dst, nbytes)
+    out = new_watch_hist(n_keys, n_bins, ts.device) if out is None else out
+    if len(out) < 2:
+        raise ValueError("out: (count, bytes[, dropped]) expected")
+    _sized(out[0], 8, 2 * n_keys * n_bins, "count")
+    _sized(out[1], 8, 2 * n_keys * n_bins, "bytes")
+    if len(out) > 2:
+        _sized(out[2], 8, 4, "dropped")
+    c = Columns(_ptr(ts), _ptr(src), _ptr(dst), _ptr(nbytes), n)
+    w = Window(t0, width, n_bins)
+    h = _hist_struct(out)
+    _check(_lib.sinet_watch_histogram(wlist.handle, ctypes.byref(c), ctypes.byref(w), n_keys,
+                                      ctypes.byref(h), int(accumulate), _stream(ts.device)),
+           "sinet_watch_histogram")
+    return out
 
 
 def mlp_loss_grad(params, x, y):

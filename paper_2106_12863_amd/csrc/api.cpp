@@ -258,6 +258,8 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
     }
     sinet_table* t = new sinet_table();
     t->kind = kind;
+    t->max_inst = 0;
+    for (size_t i = 0; i < P; ++i) t->max_inst = std::max(t->max_inst, id[i]);
     t->n_prefix = n_prefix;
     (void)hipGetDevice(&t->device);
     build_intervals(cb, ln, t->B, t->owner);
@@ -630,6 +632,40 @@ sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols, con
     p.n_bins = win->n_bins;
     p.magic = div_magic(win->width_ms);
     return run_hist(p, PASS_LABEL | PASS_HIST, accumulate, stream);
+}
+
+sinet_status sinet_watch_histogram(const sinet_table* list, const sinet_columns* cols,
+                                   const sinet_window* win, uint32_t n_keys,
+                                   sinet_watch_hist* out, int accumulate, hipStream_t stream) {
+    sinet_status st = check_usable(list);
+    if (st != SINET_OK) return st;
+    st = check_window(win);
+    if (st != SINET_OK) return st;
+    if (!cols) return fail(SINET_ERR_INVALID_ARG, "columns are NULL");
+    if (!out || !out->count || !out->bytes) return fail(SINET_ERR_INVALID_ARG, "watch output is NULL");
+    if (n_keys == 0) return fail(SINET_ERR_INVALID_ARG, "n_keys is 0");
+    if (list->n_prefix && list->max_inst >= n_keys)
+        return fail(SINET_ERR_INVALID_ARG, "a key (inst id) of the list is not below n_keys");
+    if (2ull * n_keys * win->n_bins > (1ull << 40))
+        return fail(SINET_ERR_INVALID_ARG, "2 * n_keys * n_bins above 2^40");
+    if (cols->n && (!cols->ts || !cols->src || !cols->dst || !cols->bytes))
+        return fail(SINET_ERR_INVALID_ARG, "column is NULL");
+    PassParams p;
+    memset(&p, 0, sizeof(p));
+    p.t = list->dev;
+    p.ts = cols->ts;
+    p.src = cols->src;
+    p.dst = cols->dst;
+    p.bytes = cols->bytes;
+    p.count = (unsigned long long*)out->count;
+    p.hbytes = (unsigned long long*)out->bytes;
+    p.dropped = (unsigned long long*)out->dropped;
+    p.n = cols->n;
+    p.t0 = win->t0_ms;
+    p.width = win->width_ms;
+    p.n_bins = win->n_bins;
+    p.magic = div_magic(win->width_ms);
+    return run_watch(p, n_keys, accumulate, stream);
 }
 
 sinet_status sinet_mlp_loss_grad(const float* params, const float* x, const float* y, uint64_t n,

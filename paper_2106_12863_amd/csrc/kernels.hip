@@ -1557,6 +1557,162 @@ __global__ void k_zero_jobs(const ZeroJob* __restrict__ jobs, uint32_t n_jobs) {
 }
 
 // ---------------------------------------------------------------------------
+// Watch-list histograms (sections "AbuseIPDB" and "GRIZZLY STEPPE", Figures
+// 8-11): the sessions of listed hosts per time window, in both directions.
+// The list is a prefix table whose institution ids are the keys.  Each
+// session looks up its source and its destination; a match adds (1, bytes)
+// to cell [dir][key][bin] (dir 0: the source matched, 1: the destination),
+// or to dropped[dir] outside the window.  Listed sessions are few, so the
+// pass is a streaming read of the address columns: the /16 filter in LDS
+// rejects most addresses with one LDS read, only addresses in blocks the
+// list touches run the interval search, and the timestamps and byte counts
+// are loaded only for a lane whose four sessions include a match.  Small
+// histograms live in LDS per workgroup (merged with atomics at the end);
+// larger ones take device-scope atomics directly.
+// ---------------------------------------------------------------------------
+constexpr int kWatchBlock = 256;
+constexpr uint32_t kWatchPrivCells = 4096;  // [2][n_keys][n_bins] cells kept in LDS
+
+struct WatchParams {
+    PassParams p;     // list table, columns, window; count/hbytes [2][n_keys][n_bins], dropped [2][2]
+    uint32_t n_keys;
+    uint32_t vec;     // 16-byte loads allowed
+};
+
+// Longest-match row + 1 (0: no match) of each address.
+template <uint32_t KIND, int N>
+__device__ __forceinline__ void owners(const DevTable& t, const LdsView& v, const uint32_t* a,
+                                       uint32_t* code) {
+    if constexpr (KIND == KK_SCAN) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) code[q] = scan_owner(t, v, a[q]);
+    } else {
+        uint32_t need = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            code[q] = 0;
+            const uint32_t st = (v.filter[a[q] >> 20] >> (((a[q] >> 16) & 15u) * 2)) & 3u;
+            need |= (st != 0u ? 1u : 0u) << q;
+        }
+        if (need) {
+            uint32_t j[N];
+            intervals<KIND, N>(t, v, a, j, need);
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                if ((need >> q) & 1u) code[q] = *glob(t.owner + j[q]);
+        }
+    }
+}
+
+struct WatchDropped {
+    unsigned long long c[2], b[2];
+    __device__ __forceinline__ void add(uint32_t dir, uint64_t nbytes) {
+        c[dir] += 1;
+        b[dir] += nbytes;
+    }
+    __device__ __forceinline__ void flush(unsigned long long* out) const {
+        if (!out) return;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            if (c[d]) {
+                atomicAdd(out + 2 * d, c[d]);
+                atomicAdd(out + 2 * d + 1, b[d]);
+            }
+        }
+    }
+};
+
+template <bool PRIV>
+__device__ __forceinline__ void watch_add(const WatchParams& w, uint32_t* hc, unsigned long long* hb,
+                                          uint32_t dir, uint32_t code, uint32_t ts, uint64_t nbytes,
+                                          WatchDropped& d) {
+    uint32_t bin;
+    if (!in_window(w.p, ts, bin)) {
+        d.add(dir, nbytes);
+        return;
+    }
+    const uint32_t key = *glob(w.p.t.inst + (code - 1));
+    const uint64_t k = ((uint64_t)dir * w.n_keys + key) * w.p.n_bins + bin;
+    if constexpr (PRIV) {
+        atomicAdd(hc + k, 1u);
+        atomicAdd(hb + k, (unsigned long long)nbytes);
+    } else {
+        __hip_atomic_fetch_add(w.p.count + k, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(w.p.hbytes + k, (unsigned long long)nbytes, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <uint32_t KIND, bool PRIV>
+__global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    uint32_t used = 0;
+    const PassParams& p = w.p;
+    const LdsView v = stage_lds<KIND>(p.t, lds, &used);
+    uint32_t* hc = nullptr;
+    unsigned long long* hb = nullptr;
+    const uint32_t cells = 2u * w.n_keys * p.n_bins;  // < kWatchPrivCells when PRIV
+    if constexpr (PRIV) {
+        used = (used + 1) & ~1u;
+        hb = reinterpret_cast<unsigned long long*>(lds + used);
+        hc = lds + used + 2 * cells;
+        for (uint32_t k = threadIdx.x; k < cells; k += blockDim.x) {
+            hb[k] = 0;
+            hc[k] = 0;
+        }
+        __syncthreads();
+    }
+    WatchDropped d{};
+    const uint64_t groups = (p.n + 3) / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += stride) {
+        const uint64_t i = g * 4;
+        if (w.vec && i + 4 <= p.n) {
+            const uint4 s4 = gload4(p.src + i), d4 = gload4(p.dst + i);
+            const uint32_t a[8] = {s4.x, s4.y, s4.z, s4.w, d4.x, d4.y, d4.z, d4.w};
+            uint32_t code[8];
+            owners<KIND, 8>(p.t, v, a, code);
+            uint32_t any = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) any |= code[q];
+            if (any) {
+                const uint4 t4 = gload4(p.ts + i);
+                const ulonglong2 b01 = gload2(p.bytes + i), b23 = gload2(p.bytes + i + 2);
+                const uint32_t ts[4] = {t4.x, t4.y, t4.z, t4.w};
+                const uint64_t by[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (code[q]) watch_add<PRIV>(w, hc, hb, q >> 2, code[q], ts[q & 3], by[q & 3], d);
+            }
+        } else {
+            for (uint64_t e = i; e < p.n && e < i + 4; ++e) {
+                const uint32_t a[2] = {*glob(p.src + e), *glob(p.dst + e)};
+                uint32_t code[2];
+                owners<KIND, 2>(p.t, v, a, code);
+                if (code[0] | code[1]) {
+                    const uint32_t ts = *glob(p.ts + e);
+                    const uint64_t by = *glob(p.bytes + e);
+                    for (uint32_t dir = 0; dir < 2; ++dir)
+                        if (code[dir]) watch_add<PRIV>(w, hc, hb, dir, code[dir], ts, by, d);
+                }
+            }
+        }
+    }
+    d.flush(p.dropped);
+    if constexpr (PRIV) {
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < cells; k += blockDim.x) {
+            if (hc[k]) {
+                __hip_atomic_fetch_add(p.count + k, (unsigned long long)hc[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(p.hbytes + k, hb[k], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 using PassFn = void (*)(PassParams, FarList);
@@ -2127,6 +2283,57 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
         acc = 1;
     }
     return SINET_OK;
+}
+
+
+// ---- watch-list histograms ----------------------------------------------------
+using WatchFn = void (*)(WatchParams);
+
+template <uint32_t KIND>
+static WatchFn watch_fn(bool priv) {
+    return priv ? k_watch<KIND, true> : k_watch<KIND, false>;
+}
+
+static WatchFn pick_watch(uint32_t kind, bool priv) {
+    switch (kind) {
+        case KK_SCAN: return watch_fn<KK_SCAN>(priv);
+        case KK_BSEARCH: return watch_fn<KK_BSEARCH>(priv);
+        case KK_TRIE: return watch_fn<KK_TRIE>(priv);
+        case KK_PLA: return watch_fn<KK_PLA>(priv);
+        case KK_MLP: return watch_fn<KK_MLP>(priv);
+        default: return nullptr;
+    }
+}
+
+sinet_status run_watch(const PassParams& p, uint32_t n_keys, int accumulate, hipStream_t s) {
+    const uint64_t cells = 2ull * n_keys * p.n_bins;
+    sinet_status st = SINET_OK;
+    if (!accumulate) {
+        st = launch_zero(p.count, cells, s);
+        if (st == SINET_OK) st = launch_zero(p.hbytes, cells, s);
+        if (st == SINET_OK && p.dropped) st = launch_zero(p.dropped, 4, s);
+        if (st != SINET_OK) return st;
+    }
+    if (p.n == 0) return SINET_OK;
+    const uint32_t kind = p.t.kind;
+    const size_t table_lds = (size_t)p.t.lds_bytes + 8;
+    const bool priv = cells <= kWatchPrivCells && table_lds + 12 * cells + 8 <= 64 * 1024;
+    WatchFn fn = pick_watch(kind, priv);
+    if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no watch kernel for this lookup kind");
+    const size_t lds = table_lds + (priv ? 12 * cells + 8 : 0);
+    if (lds > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
+    WatchParams w;
+    w.p = p;
+    w.n_keys = n_keys;
+    w.vec = aligned16(p.src) && aligned16(p.dst) && aligned16(p.ts) && aligned16(p.bytes) ? 1u : 0u;
+    uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)fn, kWatchBlock, lds);
+    const uint64_t tiles = ((p.n + 3) / 4 + kWatchBlock - 1) / kWatchBlock;
+    if (grid > tiles) grid = tiles;
+    if (grid < 1) grid = 1;
+    count_timed_call();
+    PhaseScope ph(PH_LOOKUP, s);
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kWatchBlock), lds, s, w);
+    return check_hip(hipGetLastError(), "watch kernel launch");
 }
 
 }  // namespace sinet

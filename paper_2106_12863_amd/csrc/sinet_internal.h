@@ -168,6 +168,7 @@ struct sinet_table {
     uint32_t segments;
     int device;
     uint32_t lds_words;         // per-workgroup LDS budget in 32-bit words
+    uint32_t max_inst;          // largest inst id (watch-list keys must exceed it)
     // host copies used by training and tests
     std::vector<uint32_t> B, owner;
 };
@@ -206,6 +207,9 @@ PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins);
 sinet_status run_partitioned(const PassParams& p, uint32_t kind, const PartWs& w, int accumulate,
                              hipStream_t s);
 int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n);
+// Watch-list histograms: count/hbytes [2][n_keys][n_bins], dropped [2][2]
+// (cleared first unless accumulate); the table's inst ids are the keys.
+sinet_status run_watch(const PassParams& p, uint32_t n_keys, int accumulate, hipStream_t s);
 sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s);
 sinet_status ws_free(void* ptr, hipStream_t s);
 uint32_t device_cu_count();

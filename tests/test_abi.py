@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for must in ("sinet_discriminate", "sinet_histogram", "sinet_pipeline", "sinet_table_create",
                  "sinet_table_train", "sinet_batch_plan_create", "sinet_batch_run",
-                 "sinet_autotune", "sinet_mlp_loss_grad"):
+                 "sinet_autotune", "sinet_mlp_loss_grad", "sinet_watch_histogram"):
         assert must in names
 
 
@@ -70,6 +70,8 @@ def test_host_side_argument_errors():
     assert lib.sinet_pipeline(None, ctypes.byref(cols), ctypes.byref(w), None, ctypes.byref(h), 0,
                               None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_discriminate(None, P(16), P(16), 4, P(16), None, None, None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_watch_histogram(None, ctypes.byref(cols), ctypes.byref(w), 3, ctypes.byref(h), 0,
+                                     None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_mlp_loss_grad(None, P(16), P(16), 4, P(16), P(16), None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_batch_plan_create(None, 0, None, None, ctypes.byref(out)) != sinet.OK
     assert lib.sinet_status_string(2) == b"out of device memory"
