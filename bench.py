@@ -24,6 +24,8 @@ Forms timed on the same resident day (the first is the headline value):
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5|4|2|3]
                     [--forms plain,bsearch,...] [--no-cpu]
+    python bench.py --watch    watch-list histograms over the full day
+                               (two synthetic lists, 1,177 hosts, 10-min bins)
 """
 from __future__ import annotations
 
@@ -45,9 +47,9 @@ DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched,batched_pla"
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
 COUNTER_TRAFFIC = {
-    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "061c96277ad7c13c",
+    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "b2ed44c0f83cd82c",
                  "bytes": 40.32e9},
-    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "061c96277ad7c13c",
+    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "b2ed44c0f83cd82c",
                  "bytes": 12.98e9},
 }
 KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")
@@ -68,6 +70,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--day-streams", type=int, default=24, help="streams of the batched day")
+    ap.add_argument("--watch", action="store_true",
+                    help="watch-list histograms over the full day instead of the default forms")
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="only run a plain device copy of this many GB (counter calibration)")
     return ap.parse_args()
@@ -332,6 +336,75 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
     }
 
 
+def bench_watch(args, torch, sinet, sinetgen, gg):
+    """Watch-list histograms (sections "AbuseIPDB" and "GRIZZLY STEPPE") over
+    the full synthetic day: the two synthetic lists' 1,177 hosts placed in
+    0.2% of the sources and of the destinations, one key per host, 10-minute
+    bins, both directions."""
+    import numpy as np
+    wl = sinetgen.config(5, n=args.n or None)
+    wlist = sinetgen.watch_lists()
+    log(f"watch: {wl.n} sessions, {wlist.n} listed hosts")
+    cols = gg.alloc_and_fill(wl)
+    gg.watch_fill(wlist, cols["src"], cols["dst"])
+    plen = np.full(wlist.n, 32, np.uint8)
+    tab = sinet.Table(wlist.addrs, plen, kind="bsearch")
+    t0, width, n_bins, n_keys = 0, 600_000, 144, wlist.n
+    out = sinet.new_watch_hist(n_keys, n_bins)
+
+    def step():
+        sinet.watch_histogram(tab, cols["ts"], cols["src"], cols["dst"], cols["bytes"], t0, width,
+                              n_bins, n_keys, out=out)
+
+    ms, ms_min, wall, ph = time_calls(torch, step, args.steps, args.warmup, sinet=sinet)
+    addrs = torch.from_numpy(wlist.addrs.view(np.int32)).cuda()
+    ls, ld = torch.isin(cols["src"], addrs), torch.isin(cols["dst"], addrs)
+    matched = int((ls | ld).sum())
+    cells = 2 * n_keys * n_bins
+    # what the method must move: both addresses of every session, the time
+    # and byte count of the sessions with a listed endpoint, every cell once
+    alg = 8 * wl.n + 12 * matched + 16 * cells
+    launch_ms = ph["lookup_ms"] / max(1, ph["calls"])
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    workload = f"watch-fullday-{wl.n:.2g}-{wlist.n}hosts-{n_bins}x10min"
+    line = {
+        "metric": "sessions/sec watch-list histograms on 1 GPU, % HBM roofline",
+        "value": wl.n / (ms * 1e-3), "unit": "sessions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32,u64",
+        "data": "synthetic (seeded SINET-shaped day with synthetic watch lists, generated in HBM)",
+        "config": {"workload": workload, "n_sessions": wl.n, "listed_hosts": wlist.n,
+                   "lists": [int(x) for x in np.bincount(wlist.lists)], "keys": "per host",
+                   "n_bins": n_bins, "bin_ms": width, "listed_share": wlist.frac,
+                   "sessions_with_a_listed_end": matched, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_watch", workload), "kernel": "k_watch",
+                     "alg_bytes_per_launch": alg, "launch_ms": launch_ms,
+                     "launches": ph["calls"], "steps": args.steps},
+        "forms": {"watch": {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall,
+                            "cells": cells, "listed_src": int(ls.sum()),
+                            "listed_dst": int(ld.sum())}},
+    }
+    if not args.no_cpu:
+        import oracle
+        sample = args.cpu_sample or 40_000_000
+        n = min(sample, wl.n)
+        i0 = (wl.n - n) // 2
+        s = {k: (sinet.to_host_u64(v[i0:i0 + n]) if k == "bytes" else sinet.to_host_u32(v[i0:i0 + n]))
+             for k, v in cols.items()}
+        tc = time.perf_counter()
+        oracle.watch(wlist.addrs, plen, s["ts"], s["src"], s["dst"], s["bytes"], t0, width, n_bins,
+                     n_keys)
+        sec = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": n / sec, "unit": "sessions/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"sessions [{i0}, {i0 + n}) of the same day ({n} sessions, "
+                                          f"{sec:.1f} s): per-length-hash match of both ends "
+                                          f"against the {wlist.n} hosts, {cells}-cell histogram"}
+    return line
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -352,7 +425,9 @@ def main():
     import paper_2106_12863_amd as sinet
     import sinetgen
     import sinetgen.gpu as gg
-    if args.config == 3:
+    if args.watch:
+        line = bench_watch(args, torch, sinet, sinetgen, gg)
+    elif args.config == 3:
         line = bench_batch(args, torch, sinet, sinetgen, gg)
     else:
         line = bench_day(args, torch, sinet, sinetgen, gg)

@@ -1570,13 +1570,16 @@ __global__ void k_zero_jobs(const ZeroJob* __restrict__ jobs, uint32_t n_jobs) {
 // histograms live in LDS per workgroup (merged with atomics at the end);
 // larger ones take device-scope atomics directly.
 // ---------------------------------------------------------------------------
-constexpr int kWatchBlock = 256;
+constexpr int kWatchBlock = 512;
 constexpr uint32_t kWatchPrivCells = 4096;  // [2][n_keys][n_bins] cells kept in LDS
+constexpr uint32_t kWatchLdsKeys = 8192;    // intervals whose keys are staged in LDS
 
 struct WatchParams {
-    PassParams p;     // list table, columns, window; count/hbytes [2][n_keys][n_bins], dropped [2][2]
+    PassParams p;       // list table, columns, window; count/hbytes [2][n_keys][n_bins], dropped [2][2]
     uint32_t n_keys;
-    uint32_t vec;     // 16-byte loads allowed
+    uint32_t vec;       // 16-byte loads allowed
+    uint32_t lds_keys;  // 1: key + 1 of every interval staged in LDS (m <= kWatchLdsKeys)
+    uint32_t pad;
 };
 
 // Longest-match row + 1 (0: no match) of each address.
@@ -1622,16 +1625,18 @@ struct WatchDropped {
     }
 };
 
+// code: key + 1 when is_key, else the owner row + 1 (its key read from the
+// table's inst ids).
 template <bool PRIV>
 __device__ __forceinline__ void watch_add(const WatchParams& w, uint32_t* hc, unsigned long long* hb,
-                                          uint32_t dir, uint32_t code, uint32_t ts, uint64_t nbytes,
-                                          WatchDropped& d) {
+                                          uint32_t dir, uint32_t code, bool is_key, uint32_t ts,
+                                          uint64_t nbytes, WatchDropped& d) {
     uint32_t bin;
     if (!in_window(w.p, ts, bin)) {
         d.add(dir, nbytes);
         return;
     }
-    const uint32_t key = *glob(w.p.t.inst + (code - 1));
+    const uint32_t key = is_key ? code - 1 : *glob(w.p.t.inst + (code - 1));
     const uint64_t k = ((uint64_t)dir * w.n_keys + key) * w.p.n_bins + bin;
     if constexpr (PRIV) {
         atomicAdd(hc + k, 1u);
@@ -1643,15 +1648,88 @@ __device__ __forceinline__ void watch_add(const WatchParams& w, uint32_t* hc, un
     }
 }
 
+// Match codes of the lane's eight addresses (four sources, four
+// destinations): key + 1 from the LDS key array when given, else the owner
+// row + 1 from device memory, 0 for no match; the interval search is shared
+// by the wave: an address whose /16 block
+// the list touches goes to the wave's queue in LDS (slots ordered by address
+// number, then lane, from ballots), the wave searches the queue 64 entries at
+// a time (one entry per lane) and each lane reads its answers back.  Few
+// addresses need the search, so a wave runs one round of it rather than
+// eight searches in every lane.  Ballots see only the lanes running the call,
+// so lanes a branch masked off neither add entries nor take them.  The queue
+// is only touched by its own wave,
+// whose LDS operations complete in order; the wavefront fences keep the
+// compiler from moving them across each other.
+template <uint32_t KIND>
+__device__ __forceinline__ void owners8_shared(const DevTable& t, const LdsView& v, const uint32_t* a,
+                                               uint32_t* queue, const uint32_t* lkey, uint32_t* code) {
+    uint32_t need = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        code[q] = 0;
+        const uint32_t st = (v.filter[a[q] >> 20] >> (((a[q] >> 16) & 15u) * 2)) & 3u;
+        need |= (st != 0u ? 1u : 0u) << q;
+    }
+    if (__ballot(need != 0u) == 0ull) return;
+    uint32_t slot[8];
+    uint32_t total = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint64_t m = __ballot((need >> q) & 1u);
+        slot[q] = total + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if ((need >> q) & 1u) queue[slot[q]] = a[q];
+        total += (uint32_t)__popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // the lanes running this call (a branch may have masked some off) take
+    // the queue's entries in turn
+    const uint64_t act = __ballot(1);
+    const uint32_t n_act = (uint32_t)__popcll(act);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    for (uint32_t b = 0; b < total; b += n_act) {
+        const uint32_t k = b + rank;
+        if (k < total) {
+            const uint32_t x = queue[k];
+            uint32_t j;
+            intervals<KIND, 1>(t, v, &x, &j, 1u);
+            queue[k] = lkey ? lkey[j] : *glob(t.owner + j);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if ((need >> q) & 1u) code[q] = queue[slot[q]];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the queue is reused next tile
+}
+
 template <uint32_t KIND, bool PRIV>
 __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint32_t used = 0;
     const PassParams& p = w.p;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
+    // each wave's search queue: eight addresses per lane at most
+    uint32_t* queue = lds + used + (threadIdx.x >> 6) * 512u;
+    if constexpr (KIND != KK_SCAN) used += (kWatchBlock / 64) * 512u;
+    // key + 1 (0: no match) of every interval, when the list is small enough
+    uint32_t* lkey = nullptr;
+    if constexpr (KIND != KK_SCAN) {
+        if (w.lds_keys) {
+            lkey = lds + used;
+            for (uint32_t j = threadIdx.x; j < p.t.m; j += blockDim.x) {
+                const uint32_t o = *glob(p.t.owner + j);
+                lkey[j] = o ? *glob(p.t.inst + (o - 1)) + 1u : 0u;
+            }
+            used += p.t.m;
+            __syncthreads();
+        }
+    }
     uint32_t* hc = nullptr;
     unsigned long long* hb = nullptr;
-    const uint32_t cells = 2u * w.n_keys * p.n_bins;  // < kWatchPrivCells when PRIV
+    const uint32_t cells = 2u * w.n_keys * p.n_bins;  // <= kWatchPrivCells when PRIV
     if constexpr (PRIV) {
         used = (used + 1) & ~1u;
         hb = reinterpret_cast<unsigned long long*>(lds + used);
@@ -1665,13 +1743,27 @@ __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
     WatchDropped d{};
     const uint64_t groups = (p.n + 3) / 4;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += stride) {
+    // the next group's addresses are loaded while this one is looked up
+    auto full = [&](uint64_t g) { return w.vec && g * 4 + 4 <= p.n; };
+    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint4 cs = make_uint4(0, 0, 0, 0), cd = cs;
+    if (g < groups && full(g)) {
+        cs = gload4(p.src + g * 4);
+        cd = gload4(p.dst + g * 4);
+    }
+    for (; g < groups; g += stride) {
         const uint64_t i = g * 4;
-        if (w.vec && i + 4 <= p.n) {
-            const uint4 s4 = gload4(p.src + i), d4 = gload4(p.dst + i);
+        uint4 ns = cs, nd = cd;
+        if (g + stride < groups && full(g + stride)) {
+            ns = gload4(p.src + (g + stride) * 4);
+            nd = gload4(p.dst + (g + stride) * 4);
+        }
+        if (full(g)) {
+            const uint4 s4 = cs, d4 = cd;
             const uint32_t a[8] = {s4.x, s4.y, s4.z, s4.w, d4.x, d4.y, d4.z, d4.w};
             uint32_t code[8];
-            owners<KIND, 8>(p.t, v, a, code);
+            if constexpr (KIND == KK_SCAN) owners<KIND, 8>(p.t, v, a, code);
+            else owners8_shared<KIND>(p.t, v, a, queue, lkey, code);
             uint32_t any = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) any |= code[q];
@@ -1682,7 +1774,9 @@ __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
                 const uint64_t by[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    if (code[q]) watch_add<PRIV>(w, hc, hb, q >> 2, code[q], ts[q & 3], by[q & 3], d);
+                    if (code[q])
+                        watch_add<PRIV>(w, hc, hb, q >> 2, code[q], lkey != nullptr, ts[q & 3],
+                                        by[q & 3], d);
             }
         } else {
             for (uint64_t e = i; e < p.n && e < i + 4; ++e) {
@@ -1693,10 +1787,12 @@ __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
                     const uint32_t ts = *glob(p.ts + e);
                     const uint64_t by = *glob(p.bytes + e);
                     for (uint32_t dir = 0; dir < 2; ++dir)
-                        if (code[dir]) watch_add<PRIV>(w, hc, hb, dir, code[dir], ts, by, d);
+                        if (code[dir]) watch_add<PRIV>(w, hc, hb, dir, code[dir], false, ts, by, d);
                 }
             }
         }
+        cs = ns;
+        cd = nd;
     }
     d.flush(p.dropped);
     if constexpr (PRIV) {
@@ -2316,7 +2412,12 @@ sinet_status run_watch(const PassParams& p, uint32_t n_keys, int accumulate, hip
     }
     if (p.n == 0) return SINET_OK;
     const uint32_t kind = p.t.kind;
-    const size_t table_lds = (size_t)p.t.lds_bytes + 8;
+    // the table, each wave's search queue and the interval keys (interval
+    // kinds), the private cells
+    const bool lds_keys = kind != KK_SCAN && p.t.m <= kWatchLdsKeys;
+    const size_t table_lds = (size_t)p.t.lds_bytes +
+                             (kind == KK_SCAN ? 0 : 4 * 512 * (kWatchBlock / 64)) +
+                             (lds_keys ? 4ull * p.t.m : 0) + 8;
     const bool priv = cells <= kWatchPrivCells && table_lds + 12 * cells + 8 <= 64 * 1024;
     WatchFn fn = pick_watch(kind, priv);
     if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no watch kernel for this lookup kind");
@@ -2326,6 +2427,8 @@ sinet_status run_watch(const PassParams& p, uint32_t n_keys, int accumulate, hip
     w.p = p;
     w.n_keys = n_keys;
     w.vec = aligned16(p.src) && aligned16(p.dst) && aligned16(p.ts) && aligned16(p.bytes) ? 1u : 0u;
+    w.lds_keys = lds_keys ? 1u : 0u;
+    w.pad = 0;
     uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)fn, kWatchBlock, lds);
     const uint64_t tiles = ((p.n + 3) / 4 + kWatchBlock - 1) / kWatchBlock;
     if (grid > tiles) grid = tiles;
