@@ -51,6 +51,8 @@ COUNTER_TRAFFIC = {
                  "bytes": 40.32e9},
     "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "b2ed44c0f83cd82c",
                  "bytes": 12.98e9},
+    "k_watch": {"workload": "watch-fullday-1.6e+09-1177hosts-144x10min",
+                "kernels_sha": "b2ed44c0f83cd82c", "bytes": 14.77e9},
 }
 KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")
 

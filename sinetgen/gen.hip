@@ -105,7 +105,7 @@ __global__ void k_gen(sinetgen_params p, const uint32_t* __restrict__ pbase,
 // Watch-list overlay: sessions i0 + j whose draw from the source (or
 // destination) overlay stream falls below thr get a listed host, picked as
 // floor(K * u^2) with u the draw's high word over 2^32.
-__global__ void k_watch(const uint32_t* __restrict__ addrs, uint32_t K, uint64_t key_src,
+__global__ void k_watch_overlay(const uint32_t* __restrict__ addrs, uint32_t K, uint64_t key_src,
                         uint64_t key_dst, uint32_t thr, uint64_t i0, uint64_t n,
                         uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -132,7 +132,7 @@ extern "C" int sinetgen_watch(const uint32_t* addrs, uint32_t K, uint64_t key_sr
     if (n == 0) return 0;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_watch, dim3((unsigned)blocks), dim3(256), 0, stream, addrs, K, key_src,
+    hipLaunchKernelGGL(k_watch_overlay, dim3((unsigned)blocks), dim3(256), 0, stream, addrs, K, key_src,
                        key_dst, thr, i0, n, src, dst);
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }
