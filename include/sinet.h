@@ -323,6 +323,33 @@ sinet_status sinet_batch_run(sinet_batch_plan* plan, hipStream_t stream);
 
 sinet_status sinet_batch_plan_destroy(sinet_batch_plan* plan);
 
+/* Out-of-core pipeline (the paper merges per-chunk
+ * results by addition, section "Pairwise Reduction Pattern with GPU", and its
+ * Table 3 runs out of device memory on large inputs).  A streamer owns two
+ * staging slots, each with device buffers and pinned host buffers for
+ * chunk_sessions sessions (about 42 bytes per session per slot), and its own
+ * copy stream (default priority).  Errors: INVALID_ARG (chunk_sessions 0 or
+ * above 2^31), OUT_OF_MEMORY.  Synchronous. */
+typedef struct sinet_streamer sinet_streamer;
+sinet_status sinet_streamer_create(uint64_t chunk_sessions, sinet_streamer** out);
+
+/* sinet_pipeline over columns held in HOST memory (pageable or pinned; n may
+ * exceed device memory): chunk k + 1 is copied to the device on the
+ * streamer's copy stream while chunk k is classified and binned on stream;
+ * pageable columns pass through the pinned staging (host threads copy them
+ * in), pinned ones are copied from directly.  The histogram (device, as in
+ * sinet_pipeline) is cleared first unless accumulate and summed over the
+ * chunks; host_label (HOST, n bytes) receives the labels, or NULL.  Results
+ * equal one sinet_pipeline call over the same sessions resident on the
+ * device.  The streamer must have been created on the current device.
+ * Synchronous: returns when every chunk is binned and every label is back. */
+sinet_status sinet_streamer_pipeline(sinet_streamer* s, const sinet_table* t,
+                                     const sinet_columns* host_cols, const sinet_window* win,
+                                     uint8_t* host_label, sinet_hist* out, int accumulate,
+                                     hipStream_t stream);
+
+sinet_status sinet_streamer_destroy(sinet_streamer* s);
+
 /* Device time of the phases of sinet_histogram / sinet_pipeline, summed over
  * the calls made since timing was last enabled.  Each phase is bracketed by
  * a pair of HIP events recorded on the call's own stream (none while the

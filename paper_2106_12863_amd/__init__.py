@@ -102,6 +102,10 @@ _sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                         ctypes.POINTER(Hist), I32, P])
 _sig("sinet_watch_histogram", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), U32,
                                ctypes.POINTER(Hist), I32, P])
+_sig("sinet_streamer_create", [U64, ctypes.POINTER(P)])
+_sig("sinet_streamer_pipeline", [P, P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
+                                 ctypes.POINTER(Hist), I32, P])
+_sig("sinet_streamer_destroy", [P])
 _sig("sinet_mlp_loss_grad", [P, P, P, U64, P, P, P])
 _sig("sinet_autotune", [P, U32, ctypes.c_char_p, P, ctypes.POINTER(Tune)])
 _sig("sinet_batch_plan_create", [P, U32, ctypes.POINTER(Tune), P, ctypes.POINTER(P)])
@@ -390,6 +394,61 @@ def watch_histogram(wlist: Table, ts, src, dst, nbytes, t0: int, width: int, n_b
                                       ctypes.byref(h), int(accumulate), _stream(ts.device)),
            "sinet_watch_histogram")
     return out
+
+
+def _host_ptr(a, esize: int, n: int, name: str):
+    """Address of a contiguous host array (numpy, or a CPU torch tensor,
+    pinned or not) of at least n elements of esize bytes."""
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"] or a.itemsize != esize or a.size < n:
+            raise ValueError(f"{name}: contiguous array of {n} {esize}-byte elements expected")
+        return P(a.ctypes.data)
+    if getattr(a, "is_cuda", True) or not a.is_contiguous() or a.element_size() != esize \
+            or a.numel() < n:
+        raise ValueError(f"{name}: contiguous host tensor of {n} {esize}-byte elements expected")
+    return P(a.data_ptr())
+
+
+class Streamer:
+    """Out-of-core pipeline: columns in host memory streamed through two
+    device staging slots of `chunk` sessions each (see sinet_streamer_*)."""
+
+    def __init__(self, chunk: int = 64 << 20):
+        out = P()
+        _check(_lib.sinet_streamer_create(chunk, ctypes.byref(out)), "sinet_streamer_create")
+        self.handle = out
+        self.chunk = chunk
+
+    def pipeline(self, table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: int,
+                 label=True, out=None, accumulate: bool = False, device="cuda"):
+        """Host columns (numpy or CPU tensors) -> (host labels or None, device histogram)."""
+        n = len(ts)
+        c = Columns(_host_ptr(ts, 4, n, "ts"), _host_ptr(src, 4, n, "src"),
+                    _host_ptr(dst, 4, n, "dst"), _host_ptr(nbytes, 8, n, "bytes"), n)
+        for a, name in ((src, "src"), (dst, "dst"), (nbytes, "bytes")):
+            if len(a) != n:
+                raise ValueError(f"{name}: {len(a)} elements, ts has {n}")
+        lab = np.empty(n, np.uint8) if label is True else (None if label in (None, False) else label)
+        lp = None if lab is None else _host_ptr(lab, 1, n, "label")
+        out = new_hist(n_bins, device) if out is None else out
+        _check_hist(out, n_bins)
+        w = Window(t0, width, n_bins)
+        h = _hist_struct(out)
+        _check(_lib.sinet_streamer_pipeline(self.handle, table.handle, ctypes.byref(c),
+                                            ctypes.byref(w), lp, ctypes.byref(h), int(accumulate),
+                                            _stream(out[0].device)), "sinet_streamer_pipeline")
+        return lab, out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.sinet_streamer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mlp_loss_grad(params, x, y):
