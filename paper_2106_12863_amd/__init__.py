@@ -428,7 +428,12 @@ class Streamer:
         for a, name in ((src, "src"), (dst, "dst"), (nbytes, "bytes")):
             if len(a) != n:
                 raise ValueError(f"{name}: {len(a)} elements, ts has {n}")
-        lab = np.empty(n, np.uint8) if label is True else (None if label in (None, False) else label)
+        if label is True:
+            lab = np.empty(n, np.uint8)
+        elif label is None or label is False:
+            lab = None
+        else:
+            lab = label
         lp = None if lab is None else _host_ptr(lab, 1, n, "label")
         out = new_hist(n_bins, device) if out is None else out
         _check_hist(out, n_bins)
