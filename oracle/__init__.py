@@ -59,6 +59,8 @@ def lib():
         L.or_watch.argtypes = [P, P, P, u64, i32, P, P, P, P, u64, u32, u32, u32, u32,
                                P, P, P, i32]
         L.or_watch.restype = i32
+        L.or_rebin.argtypes = [P, u64, u64, u64, P]
+        L.or_rebin.restype = i32
         L.or_endpoints.argtypes = [P, P, u64, P, P]
         L.or_endpoints.restype = ctypes.c_int64
         _lib = L
@@ -176,6 +178,19 @@ def watch(base, plen, ts, src, dst, nbytes, t0, width, n_bins, n_keys, inst=None
         raise ValueError("a key is not below n_keys")
     assert rc == 0
     return cnt, byt, drp
+
+
+def rebin(a, factor: int):
+    """Coarser frames of a [..., n_bins] uint64 histogram: every group of
+    ``factor`` consecutive bins summed (the last group may be shorter)."""
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    n_bins = a.shape[-1]
+    rows = int(np.prod(a.shape[:-1], dtype=np.int64)) if a.ndim > 1 else 1
+    n_out = -(-n_bins // factor)
+    out = np.empty(a.shape[:-1] + (n_out,), np.uint64)
+    rc = lib().or_rebin(_p(a), rows, n_bins, factor, _p(out))
+    assert rc == 0
+    return out
 
 
 def endpoints(base, plen):

@@ -268,6 +268,27 @@ int or_watch(const uint32_t* base, const uint8_t* len, const uint32_t* inst,
 }
 
 /* ------------------------------------------------------------------------
+ * Coarser time frames (section "All Sessions of SINET", Figures 6-7: the
+ * sessions grouped into one-hour frames): out[r][k] is the sum of
+ * in[r][b] over b = k * factor .. min((k + 1) * factor, n_bins) - 1, for
+ * every row r, k < ceil(n_bins / factor); unsigned 64-bit, modulo 2^64.
+ * ---------------------------------------------------------------------- */
+int or_rebin(const uint64_t* in, uint64_t rows, uint64_t n_bins, uint64_t factor,
+             uint64_t* out) {
+    if (rows == 0 || n_bins == 0 || factor == 0) return 1;
+    const uint64_t n_out = (n_bins + factor - 1) / factor;
+    for (uint64_t r = 0; r < rows; ++r) {
+        for (uint64_t k = 0; k < n_out; ++k) {
+            uint64_t sum = 0;
+            for (uint64_t b = k * factor; b < (k + 1) * factor && b < n_bins; ++b)
+                sum += in[r * n_bins + b];
+            out[r * n_out + k] = sum;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Elementary intervals of a prefix table (used to state what a position
  * search over sorted boundaries must return).  Every prefix p covers
  * [bitmask(base_p, Z_p), that + 2^(32-Z_p)); the sorted distinct starts and

@@ -228,3 +228,38 @@ def test_watch_overlay_rate_and_skew():
         # floor(K u^2): P(index < K/4) = P(u < 1/2) = 1/2
         assert abs((idx < wlist.n / 4).mean() - 0.5) < 0.03
     assert np.array_equal(s["ts"], s0["ts"]) and np.array_equal(s["bytes"], s0["bytes"])
+
+
+# ------------------------------------------------------------ coarser frames
+def test_rebin_equals_the_histogram_at_the_coarser_width():
+    """Figures 6-7 group the day into one-hour frames: summing every group of
+    f bins of width w gives the histogram of width w * f (floor((t - t0) / w)
+    // f == floor((t - t0) / (w * f))), with a short last frame holding only
+    the sessions of the fine window."""
+    wl = sinetgen.config(2, n=300_007)
+    s = sinetgen.sessions(wl)
+    lab = oracle.classify(wl.pbase, wl.plen, s["src"], s["dst"], want_inst=False)
+    t0, w = 40_000, 3
+    for n_bins, f in ((9_000, 1_000), (9_001, 1_000), (9_000, 7), (9_000, 1), (9_000, 9_000),
+                      (9_000, 50_000)):
+        fine_c, fine_b, _ = oracle.histogram(s["ts"], s["bytes"], lab, t0, w, n_bins)
+        n_out = -(-n_bins // f)
+        # the coarse histogram of exactly the sessions inside the fine window
+        keep = s["ts"].astype(np.int64) < t0 + w * n_bins
+        cc, cb, _ = oracle.histogram(s["ts"][keep], s["bytes"][keep], lab[keep], t0, w * f, n_out)
+        assert np.array_equal(oracle.rebin(fine_c, f), cc), (n_bins, f)
+        assert np.array_equal(oracle.rebin(fine_b, f), cb), (n_bins, f)
+
+
+def test_rebin_special_cases_and_wraparound():
+    rng = np.random.default_rng(4)
+    a = rng.integers(0, 1 << 63, (3, 101), dtype=np.int64).astype(np.uint64) * np.uint64(3)
+    assert np.array_equal(oracle.rebin(a, 1), a)
+    total = oracle.rebin(a, 500)
+    assert total.shape == (3, 1)
+    for r in range(3):
+        assert int(total[r, 0]) == sum(int(x) for x in a[r]) % (1 << 64)
+    got = oracle.rebin(a, 10)
+    for r in range(3):
+        for k in range(11):
+            assert int(got[r, k]) == sum(int(x) for x in a[r, 10 * k:10 * k + 10]) % (1 << 64)
