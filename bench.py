@@ -25,6 +25,7 @@ Forms timed on the same resident day (the first is the headline value):
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5|4|2|3]
                     [--forms plain,bsearch,...] [--no-cpu]
     python bench.py --host     the full day from host memory, streamed over PCIe
+    python bench.py --rebin    the day's 1-ms histogram summed into one-hour frames
     python bench.py --watch    watch-list histograms over the full day
                                (two synthetic lists, 1,177 hosts, 10-min bins)
 """
@@ -73,6 +74,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--day-streams", type=int, default=24, help="streams of the batched day")
+    ap.add_argument("--rebin", action="store_true",
+                    help="the day's millisecond histogram summed into one-hour frames")
     ap.add_argument("--host", action="store_true",
                     help="the plain pipeline over the full day held in host memory (streamed)")
     ap.add_argument("--watch", action="store_true",
@@ -341,6 +344,43 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
     }
 
 
+def bench_rebin(args, torch, sinet, sinetgen, gg):
+    """The full day's millisecond histogram (4 x 86.4 M count and byte bins,
+    5.53 GB) summed into 24 one-hour frames, as in the paper's Figures 6-7."""
+    wl = sinetgen.config(5, n=args.n or None)
+    w = wl.window
+    cols = gg.alloc_and_fill(wl)
+    tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch")
+    _, (c, b, _) = sinet.pipeline(tab, cols["ts"], cols["src"], cols["dst"], cols["bytes"], w.t0,
+                                  w.width, w.n_bins)
+    del cols
+    factor = 3_600_000
+    oc = sinet.rebin(c, factor)
+    ob = sinet.rebin(b, factor)
+
+    def step():
+        sinet.rebin(c, factor, out=oc)
+        sinet.rebin(b, factor, out=ob)
+
+    ms, ms_min, wall, _ = time_calls(torch, step, args.steps, args.warmup)
+    alg = 2 * 8 * 4 * w.n_bins  # every millisecond bin read once
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {
+        "metric": "bins/sec summed into one-hour frames on 1 GPU, % HBM roofline",
+        "value": 2 * 4 * w.n_bins / (ms * 1e-3), "unit": "bins/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic (the full synthetic day's histogram, computed in HBM)",
+        "config": {"workload": "rebin-4x86.4M1ms-to-24x1h", "n_bins": w.n_bins, "factor": factor,
+                   "arrays": 2, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rebin_tiles (two launches per step)",
+                     "alg_bytes_per_launch": alg / 2, "launch_ms": ms / 2},
+        "forms": {"rebin": {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall}},
+    }
+
+
 def bench_host(args, torch, sinet, sinetgen, gg):
     """The plain pipeline over the full synthetic day held in host memory
     (pinned, then pageable), streamed through the device in chunks: the
@@ -499,6 +539,8 @@ def main():
         line = bench_watch(args, torch, sinet, sinetgen, gg)
     elif args.host:
         line = bench_host(args, torch, sinet, sinetgen, gg)
+    elif args.rebin:
+        line = bench_rebin(args, torch, sinet, sinetgen, gg)
     elif args.config == 3:
         line = bench_batch(args, torch, sinet, sinetgen, gg)
     else:

@@ -323,6 +323,18 @@ sinet_status sinet_batch_run(sinet_batch_plan* plan, hipStream_t stream);
 
 sinet_status sinet_batch_plan_destroy(sinet_batch_plan* plan);
 
+/* Coarser time frames (section "All Sessions of SINET", Figures 6-7: the
+ * sessions grouped into one-hour frames, here from the millisecond bins).
+ * in: [rows][n_bins] and out: [rows][ceil(n_bins / factor)] unsigned 64-bit
+ * device arrays, row-major; out[r][k] = sum of in[r][b] over b = k * factor
+ * .. min((k + 1) * factor, n_bins) - 1, modulo 2^64 (the last frame may be
+ * shorter).  out is overwritten.  rows is 4 for a label histogram, 2 * n_keys
+ * for a watch-list histogram; count and byte arrays are separate calls.
+ * Errors: INVALID_ARG (NULL pointer, rows, n_bins or factor 0).
+ * Asynchronous. */
+sinet_status sinet_rebin(const uint64_t* in, uint32_t rows, uint32_t n_bins, uint32_t factor,
+                         uint64_t* out, hipStream_t stream);
+
 /* Out-of-core pipeline (the paper merges per-chunk
  * results by addition, section "Pairwise Reduction Pattern with GPU", and its
  * Table 3 runs out of device memory on large inputs).  A streamer owns two

@@ -102,6 +102,7 @@ _sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                         ctypes.POINTER(Hist), I32, P])
 _sig("sinet_watch_histogram", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), U32,
                                ctypes.POINTER(Hist), I32, P])
+_sig("sinet_rebin", [P, U32, U32, U32, P, P])
 _sig("sinet_streamer_create", [U64, ctypes.POINTER(P)])
 _sig("sinet_streamer_pipeline", [P, P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                                  ctypes.POINTER(Hist), I32, P])
@@ -393,6 +394,25 @@ def watch_histogram(wlist: Table, ts, src, dst, nbytes, t0: int, width: int, n_b
     _check(_lib.sinet_watch_histogram(wlist.handle, ctypes.byref(c), ctypes.byref(w), n_keys,
                                       ctypes.byref(h), int(accumulate), _stream(ts.device)),
            "sinet_watch_histogram")
+    return out
+
+
+def rebin(h, factor: int, out=None):
+    """Coarser frames of a [..., n_bins] int64 (uint64) device histogram:
+    every group of ``factor`` consecutive bins summed; returns [..., n_out]."""
+    import torch
+    _dev_check(h)
+    if h.element_size() != 8 or h.dim() < 1:
+        raise ValueError("h: a [..., n_bins] tensor of 8-byte elements expected")
+    n_bins = h.shape[-1]
+    rows = h.numel() // n_bins if n_bins else 0
+    n_out = -(-n_bins // factor) if factor > 0 else 0
+    if out is None:
+        out = torch.empty(tuple(h.shape[:-1]) + (n_out,), dtype=h.dtype, device=h.device)
+    _dev_check(out)
+    _sized(out, 8, rows * n_out, "out")
+    _check(_lib.sinet_rebin(_ptr(h), rows, n_bins, factor, _ptr(out), _stream(h.device)),
+           "sinet_rebin")
     return out
 
 

@@ -210,6 +210,9 @@ int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n)
 // Watch-list histograms: count/hbytes [2][n_keys][n_bins], dropped [2][2]
 // (cleared first unless accumulate); the table's inst ids are the keys.
 sinet_status run_watch(const PassParams& p, uint32_t n_keys, int accumulate, hipStream_t s);
+// Coarser time frames: out[r][k] = sum of in[r][k * factor ..] (rebin.hip).
+sinet_status run_rebin(const uint64_t* in, uint64_t rows, uint64_t n_bins, uint32_t factor,
+                       uint64_t* out, hipStream_t s);
 sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s);
 sinet_status ws_free(void* ptr, hipStream_t s);
 uint32_t device_cu_count();
