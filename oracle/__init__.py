@@ -61,6 +61,8 @@ def lib():
         L.or_watch.restype = i32
         L.or_rebin.argtypes = [P, u64, u64, u64, P]
         L.or_rebin.restype = i32
+        L.or_parse.argtypes = [P, u64, ctypes.c_int64, P, P, P, P, u64, P, P]
+        L.or_parse.restype = i32
         L.or_endpoints.argtypes = [P, P, u64, P, P]
         L.or_endpoints.restype = ctypes.c_int64
         _lib = L
@@ -191,6 +193,22 @@ def rebin(a, factor: int):
     rc = lib().or_rebin(_p(a), rows, n_bins, factor, _p(out))
     assert rc == 0
     return out
+
+
+def parse(text, origin_days: int):
+    """Session text (bytes or a uint8 array) to columns: dict of ts, src,
+    dst (uint32) and bytes (uint64), plus the number of bad lines."""
+    buf = np.frombuffer(text, np.uint8) if isinstance(text, (bytes, bytearray)) else \
+        np.ascontiguousarray(text, dtype=np.uint8)
+    cap = int(np.count_nonzero(buf == 10)) + 1
+    cols = {"ts": np.empty(cap, np.uint32), "src": np.empty(cap, np.uint32),
+            "dst": np.empty(cap, np.uint32), "bytes": np.empty(cap, np.uint64)}
+    n = ctypes.c_uint64(0)
+    bad = ctypes.c_uint64(0)
+    rc = lib().or_parse(_p(buf), buf.shape[0], origin_days, _p(cols["ts"]), _p(cols["src"]),
+                        _p(cols["dst"]), _p(cols["bytes"]), cap, ctypes.byref(n), ctypes.byref(bad))
+    assert rc == 0
+    return {k: v[:n.value].copy() for k, v in cols.items()}, int(bad.value)
 
 
 def endpoints(base, plen):

@@ -289,6 +289,149 @@ int or_rebin(const uint64_t* in, uint64_t rows, uint64_t n_bins, uint64_t factor
 }
 
 /* ------------------------------------------------------------------------
+ * Session text to columns (section "Dataset Description", Table 1: the
+ * PA-7080 session record, 24 fields).  One record per line, fields in
+ * Table 1's order separated by ','.  Every '\n'-ended segment of the text
+ * is a line (an empty one included); a last segment without '\n' is a line
+ * when it is not empty.  Columns come from four fields:
+ *   1  capture_time  exactly "YYYY/MM/DD HH:MM:SS.mmm", a real calendar date
+ *                    (proleptic Gregorian), hour < 24, minute and second
+ *                    < 60; ts = its milliseconds since midnight of day
+ *                    origin_days (days since 1970-01-01), which must lie in
+ *                    [0, 2^32 - 1);
+ *   5, 8         source and destination: four decimal octets of 1-3 digits,
+ *                    each <= 255, separated by '.';
+ *   21 bytes         1-20 decimal digits, at most 2^64 - 1.
+ * A line with fewer than 21 fields or any of these fields malformed gives
+ * ts = 0xFFFFFFFF, src = dst = 0, bytes = 0 and counts as bad.
+ * ---------------------------------------------------------------------- */
+/* days since 1970-01-01 of a proleptic Gregorian date (H. Hinnant,
+ * "chrono-Compatible Low-Level Date Algorithms", days_from_civil) */
+static int64_t or_days_from_civil(int64_t y, int64_t m, int64_t d) {
+    y -= m <= 2;
+    const int64_t era = (y >= 0 ? y : y - 399) / 400;
+    const int64_t yoe = y - era * 400;
+    const int64_t doy = (153 * (m + (m > 2 ? -3 : 9)) + 2) / 5 + d - 1;
+    const int64_t doe = yoe * 365 + yoe / 4 - yoe / 100 + doy;
+    return era * 146097 + doe - 719468;
+}
+
+static int or_is_leap(int64_t y) { return (y % 4 == 0 && y % 100 != 0) || y % 400 == 0; }
+
+static int or_digits(const char* s, int n, int64_t* v) {
+    int64_t x = 0;
+    for (int i = 0; i < n; ++i) {
+        if (s[i] < '0' || s[i] > '9') return 0;
+        x = x * 10 + (s[i] - '0');
+    }
+    *v = x;
+    return 1;
+}
+
+static int or_capture_time(const char* f, uint64_t len, int64_t origin_days, uint32_t* ts) {
+    if (len != 23) return 0;
+    if (f[4] != '/' || f[7] != '/' || f[10] != ' ' || f[13] != ':' || f[16] != ':' || f[19] != '.')
+        return 0;
+    int64_t y, mo, d, h, mi, se, ms;
+    if (!or_digits(f, 4, &y) || !or_digits(f + 5, 2, &mo) || !or_digits(f + 8, 2, &d) ||
+        !or_digits(f + 11, 2, &h) || !or_digits(f + 14, 2, &mi) || !or_digits(f + 17, 2, &se) ||
+        !or_digits(f + 20, 3, &ms))
+        return 0;
+    static const int mdays[12] = {31, 28, 31, 30, 31, 30, 31, 31, 30, 31, 30, 31};
+    if (mo < 1 || mo > 12 || d < 1) return 0;
+    if (d > mdays[mo - 1] + (mo == 2 && or_is_leap(y))) return 0;
+    if (h > 23 || mi > 59 || se > 59) return 0;
+    const int64_t t = (or_days_from_civil(y, mo, d) - origin_days) * 86400000 + h * 3600000 +
+                      mi * 60000 + se * 1000 + ms;
+    if (t < 0 || t >= 0xFFFFFFFFll) return 0;
+    *ts = (uint32_t)t;
+    return 1;
+}
+
+static int or_ipv4(const char* f, uint64_t len, uint32_t* a) {
+    uint32_t v = 0;
+    uint64_t i = 0;
+    for (int part = 0; part < 4; ++part) {
+        int nd = 0;
+        uint32_t o = 0;
+        while (i < len && f[i] >= '0' && f[i] <= '9' && nd < 4) {
+            o = o * 10 + (uint32_t)(f[i] - '0');
+            ++nd;
+            ++i;
+        }
+        if (nd < 1 || nd > 3 || o > 255) return 0;
+        v = (v << 8) | o;
+        if (part < 3) {
+            if (i >= len || f[i] != '.') return 0;
+            ++i;
+        }
+    }
+    if (i != len) return 0;
+    *a = v;
+    return 1;
+}
+
+static int or_u64(const char* f, uint64_t len, uint64_t* out) {
+    if (len < 1 || len > 20) return 0;
+    uint64_t v = 0;
+    for (uint64_t i = 0; i < len; ++i) {
+        if (f[i] < '0' || f[i] > '9') return 0;
+        const uint64_t dg = (uint64_t)(f[i] - '0');
+        if (v > (UINT64_MAX - dg) / 10) return 0;
+        v = v * 10 + dg;
+    }
+    *out = v;
+    return 1;
+}
+
+/* Parse lines of text[len] into ts/src/dst/bytes (capacity cap).  Returns 0,
+ * or 1 when there are more lines than cap; *n_lines and *bad are set. */
+int or_parse(const char* text, uint64_t len, int64_t origin_days, uint32_t* ts, uint32_t* src,
+             uint32_t* dst, uint64_t* bytes, uint64_t cap, uint64_t* n_lines, uint64_t* bad) {
+    uint64_t n = 0, nbad = 0, p = 0;
+    while (p < len) {
+        uint64_t e = p;
+        while (e < len && text[e] != '\n') ++e;  /* the line is [p, e) */
+        if (n >= cap) return 1;
+        /* field boundaries: field k (1-based) is [fs[k], fe[k]) */
+        uint64_t fs[22], fe[22];
+        int nf = 0;
+        uint64_t q = p;
+        while (nf < 21) {
+            uint64_t c = q;
+            while (c < e && text[c] != ',') ++c;
+            ++nf;
+            fs[nf] = q;
+            fe[nf] = c;
+            if (c >= e) break;
+            q = c + 1;
+        }
+        uint32_t t = 0, a = 0, b = 0;
+        uint64_t by = 0;
+        int ok = nf >= 21 && or_capture_time(text + fs[1], fe[1] - fs[1], origin_days, &t) &&
+                 or_ipv4(text + fs[5], fe[5] - fs[5], &a) && or_ipv4(text + fs[8], fe[8] - fs[8], &b) &&
+                 or_u64(text + fs[21], fe[21] - fs[21], &by);
+        if (ok) {
+            ts[n] = t;
+            src[n] = a;
+            dst[n] = b;
+            bytes[n] = by;
+        } else {
+            ts[n] = 0xFFFFFFFFu;
+            src[n] = 0;
+            dst[n] = 0;
+            bytes[n] = 0;
+            ++nbad;
+        }
+        ++n;
+        p = e + 1;  /* past the '\n' (or past the end) */
+    }
+    *n_lines = n;
+    *bad = nbad;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Elementary intervals of a prefix table (used to state what a position
  * search over sorted boundaries must return).  Every prefix p covers
  * [bitmask(base_p, Z_p), that + 2^(32-Z_p)); the sorted distinct starts and
