@@ -323,6 +323,28 @@ sinet_status sinet_batch_run(sinet_batch_plan* plan, hipStream_t stream);
 
 sinet_status sinet_batch_plan_destroy(sinet_batch_plan* plan);
 
+/* Session text to columns (section "Dataset Description", Table 1: the
+ * PA-7080 session record, 24 fields).  text (device, len bytes) holds one
+ * record per line, Table 1's fields in order separated by ','; every
+ * '\n'-ended segment is a line (an empty one too), and a last segment without
+ * '\n' is a line when it is not empty.  Line i fills session i of out
+ * (device columns; out->n is their capacity):
+ *   ts    field 1, capture_time "YYYY/MM/DD HH:MM:SS.mmm" (proleptic
+ *         Gregorian), as milliseconds since midnight of day origin_days
+ *         (days since 1970-01-01), which must lie in [0, 2^32 - 1);
+ *   src   field 5, dst field 8: dotted quads of 1-3 digit octets <= 255;
+ *   bytes field 21: 1-20 decimal digits, at most 2^64 - 1.
+ * A line with fewer than 21 fields or a malformed one of these fields gives
+ * ts = 0xFFFFFFFF (outside every window), src = dst = bytes = 0, and counts
+ * in *n_bad.  *n_lines receives the number of lines.  The kernels read whole
+ * aligned 16-byte groups of text and stay inside [text, text + len).
+ * Errors: INVALID_ARG (NULL pointer, more lines than out->n: *n_lines then
+ * holds the number needed), UNSUPPORTED (text of 2^47 bytes or more),
+ * OUT_OF_MEMORY (the line index, 8 bytes per line).  Synchronous. */
+sinet_status sinet_parse_sessions(const uint8_t* text, uint64_t len, int32_t origin_days,
+                                  sinet_columns* out, uint64_t* n_lines, uint64_t* n_bad,
+                                  hipStream_t stream);
+
 /* Coarser time frames (section "All Sessions of SINET", Figures 6-7: the
  * sessions grouped into one-hour frames, here from the millisecond bins).
  * in: [rows][n_bins] and out: [rows][ceil(n_bins / factor)] unsigned 64-bit

@@ -103,6 +103,8 @@ _sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
 _sig("sinet_watch_histogram", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), U32,
                                ctypes.POINTER(Hist), I32, P])
 _sig("sinet_rebin", [P, U32, U32, U32, P, P])
+_sig("sinet_parse_sessions", [P, U64, ctypes.c_int32, ctypes.POINTER(Columns), ctypes.POINTER(U64),
+                              ctypes.POINTER(U64), P])
 _sig("sinet_streamer_create", [U64, ctypes.POINTER(P)])
 _sig("sinet_streamer_pipeline", [P, P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                                  ctypes.POINTER(Hist), I32, P])
@@ -414,6 +416,35 @@ def rebin(h, factor: int, out=None):
     _check(_lib.sinet_rebin(_ptr(h), rows, n_bins, factor, _ptr(out), _stream(h.device)),
            "sinet_rebin")
     return out
+
+
+def parse_sessions(text, origin_days: int, capacity: Optional[int] = None):
+    """Session text (a uint8 device tensor, one Table 1 record per line) to
+    columns: (dict of ts/src/dst int32 and bytes int64 device tensors of the
+    lines' count, number of bad lines)."""
+    import torch
+    _dev_check(text)
+    if text.element_size() != 1:
+        raise ValueError("text: a uint8 (or int8) device tensor expected")
+    n_bytes = text.numel()
+    cap = n_bytes // 64 + 16 if capacity is None else capacity
+    for _ in range(2):
+        cols = {"ts": torch.empty(cap, dtype=torch.int32, device=text.device),
+                "src": torch.empty(cap, dtype=torch.int32, device=text.device),
+                "dst": torch.empty(cap, dtype=torch.int32, device=text.device),
+                "bytes": torch.empty(cap, dtype=torch.int64, device=text.device)}
+        c = Columns(_ptr(cols["ts"]), _ptr(cols["src"]), _ptr(cols["dst"]), _ptr(cols["bytes"]), cap)
+        n_lines, n_bad = U64(0), U64(0)
+        st = _lib.sinet_parse_sessions(_ptr(text), n_bytes, origin_days, ctypes.byref(c),
+                                       ctypes.byref(n_lines), ctypes.byref(n_bad),
+                                       _stream(text.device))
+        if st == ERR_INVALID_ARG and n_lines.value > cap and capacity is None:
+            cap = n_lines.value  # every line counted: the second call fits
+            continue
+        _check(st, "sinet_parse_sessions")
+        n = n_lines.value
+        return {k: v[:n] for k, v in cols.items()}, n_bad.value
+    raise SinetError(ERR_INVALID_ARG, "sinet_parse_sessions")
 
 
 def _host_ptr(a, esize: int, n: int, name: str):

@@ -1,0 +1,413 @@
+// Session text to columns (section "Dataset Description", Table 1: the
+// PA-7080 session record, 24 fields).  One record per line, Table 1's fields
+// in order separated by ','; the columns come from field 1 (capture_time,
+// "YYYY/MM/DD HH:MM:SS.mmm", as milliseconds since midnight of the origin
+// day), fields 5 and 8 (source and destination, dotted quads) and field 21
+// (bytes).  Every '\n'-ended segment is a line (an empty one too); a last
+// segment without '\n' is a line when it is not empty.  A line with fewer
+// than 21 fields, an impossible date, a time outside [0, 2^32 - 1) ms of the
+// origin, an octet above 255 or a byte count above 2^64 - 1 gives
+// ts = 0xFFFFFFFF, src = dst = bytes = 0 and counts as bad.
+//
+// Three passes over the text:
+//   k_count_lines  newlines per 64 KB block (coalesced 16-byte loads);
+//   k_scan_counts  one workgroup: exclusive sums of the block counts;
+//   k_line_starts  every newline's position + 1 written at its line number;
+//   k_parse        a workgroup takes 256 consecutive lines, stages their bytes
+//                  in LDS with coalesced loads and each lane parses its line
+//                  from LDS (lines too long for LDS are read from device
+//                  memory directly).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sinet.h"
+#include "sinet_internal.h"
+
+namespace sinet {
+namespace {
+
+constexpr int kParseBlock = 256;
+constexpr uint64_t kScanBytes = 64 * 1024;    // text bytes per counting block
+constexpr uint32_t kStageBytes = 48 * 1024;   // LDS staging of a workgroup's lines
+constexpr uint32_t kBadTs = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t nl_in(uint4 v) {
+    uint32_t c = 0;
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) c += ((w[k] >> (8 * b)) & 0xFFu) == 10u ? 1u : 0u;
+    return c;
+}
+
+// Newlines of block blockIdx.x ([blk * kScanBytes, +kScanBytes) of the text).
+__global__ void __launch_bounds__(kParseBlock) k_count_lines(const uint8_t* __restrict__ text,
+                                                             uint64_t len, uint64_t* __restrict__ counts,
+                                                             uint32_t vec) {
+    __shared__ uint32_t s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanBytes;
+    const uint64_t b1 = b0 + kScanBytes < len ? b0 + kScanBytes : len;
+    uint32_t c = 0;
+    if (vec) {
+        for (uint64_t p = b0 + 16 * (uint64_t)threadIdx.x; p < b1; p += 16 * kParseBlock) {
+            if (p + 16 <= b1) {
+                c += nl_in(*reinterpret_cast<const uint4*>(text + p));
+            } else {
+                for (uint64_t q = p; q < b1; ++q) c += text[q] == 10 ? 1u : 0u;
+            }
+        }
+    } else {
+        for (uint64_t p = b0 + threadIdx.x; p < b1; p += kParseBlock) c += text[p] == 10 ? 1u : 0u;
+    }
+    atomicAdd(&s_sum, c);
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = s_sum;
+}
+
+// Exclusive sums of n counts in place, total in counts[n] (one workgroup).
+__global__ void __launch_bounds__(1024) k_scan_counts(uint64_t* __restrict__ counts, uint32_t n) {
+    __shared__ uint64_t s_part[1024];
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint64_t x = i < n ? counts[i] : 0ull;
+        s_part[threadIdx.x] = x;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+            const uint64_t y = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0ull;
+            __syncthreads();
+            s_part[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < n) counts[i] = s_carry + s_part[threadIdx.x] - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry += s_part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[n] = s_carry;
+}
+
+// starts[k + 1] = position after the k-th newline (starts[0] = 0).  Each step
+// of a block reads 16 bytes per lane; a lane's newlines are numbered after
+// the ones of the lanes before it (wave scan, then the waves in order).
+__global__ void __launch_bounds__(kParseBlock) k_line_starts(const uint8_t* __restrict__ text,
+                                                             uint64_t len,
+                                                             const uint64_t* __restrict__ first,
+                                                             uint64_t* __restrict__ starts,
+                                                             uint32_t vec) {
+    __shared__ uint32_t s_wave[kParseBlock / 64];
+    __shared__ uint64_t s_base;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanBytes;
+    const uint64_t b1 = b0 + kScanBytes < len ? b0 + kScanBytes : len;
+    if (threadIdx.x == 0) {
+        s_base = first[blockIdx.x];
+        if (blockIdx.x == 0) starts[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    for (uint64_t st = b0; st < b1; st += 16 * kParseBlock) {
+        const uint64_t p = st + 16 * (uint64_t)threadIdx.x;
+        uint32_t mask = 0;  // bit q: byte p + q is a newline
+        if (vec && p + 16 <= b1) {
+            const uint4 v = *reinterpret_cast<const uint4*>(text + p);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    mask |= (((w[k] >> (8 * q)) & 0xFFu) == 10u ? 1u : 0u) << (4 * k + q);
+        } else {
+            for (int q = 0; q < 16; ++q)
+                if (p + q < b1 && text[p + q] == 10) mask |= 1u << q;
+        }
+        const uint32_t c = (uint32_t)__popc(mask);
+        uint32_t incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+            if (lane >= (uint32_t)d) incl += y;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        uint64_t before = s_base;
+        uint32_t step_total = 0;
+        for (uint32_t w = 0; w < kParseBlock / 64; ++w) {
+            if (w < wave) before += s_wave[w];
+            step_total += s_wave[w];
+        }
+        uint64_t k = before + (incl - c);  // newlines before this lane's first
+        while (mask) {
+            const uint32_t q = (uint32_t)__builtin_ctz(mask);
+            starts[k + 1] = p + q + 1;
+            ++k;
+            mask &= mask - 1;
+        }
+        __syncthreads();  // every lane has read s_wave and s_base
+        if (threadIdx.x == 0) s_base += step_total;
+        __syncthreads();
+    }
+}
+
+// days since 1970-01-01 of a proleptic Gregorian date (H. Hinnant's
+// days_from_civil)
+__device__ __forceinline__ int64_t days_from_civil(int64_t y, int64_t m, int64_t d) {
+    y -= m <= 2 ? 1 : 0;
+    const int64_t era = (y >= 0 ? y : y - 399) / 400;
+    const int64_t yoe = y - era * 400;
+    const int64_t mp = m > 2 ? m - 3 : m + 9;
+    const int64_t doy = (153 * mp + 2) / 5 + d - 1;
+    const int64_t doe = yoe * 365 + yoe / 4 - yoe / 100 + doy;
+    return era * 146097 + doe - 719468;
+}
+
+// Byte access to one line, from LDS or from device memory.
+struct LineBytes {
+    const uint8_t* p;  // the line's first byte
+    __device__ __forceinline__ uint32_t operator[](uint64_t i) const { return p[i]; }
+};
+
+template <class Bytes>
+__device__ __forceinline__ bool dec(const Bytes& b, uint64_t at, int n, int64_t& v) {
+    int64_t x = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint32_t c = b[at + i] - '0';
+        if (c > 9u) return false;
+        x = x * 10 + c;
+    }
+    v = x;
+    return true;
+}
+
+template <class Bytes>
+__device__ bool capture_time(const Bytes& b, uint64_t s, uint64_t e, int64_t origin, uint32_t& ts) {
+    if (e - s != 23) return false;
+    if (b[s + 4] != '/' || b[s + 7] != '/' || b[s + 10] != ' ' || b[s + 13] != ':' ||
+        b[s + 16] != ':' || b[s + 19] != '.')
+        return false;
+    int64_t y, mo, d, h, mi, se, ms;
+    if (!dec(b, s, 4, y) || !dec(b, s + 5, 2, mo) || !dec(b, s + 8, 2, d) || !dec(b, s + 11, 2, h) ||
+        !dec(b, s + 14, 2, mi) || !dec(b, s + 17, 2, se) || !dec(b, s + 20, 3, ms))
+        return false;
+    if (mo < 1 || mo > 12 || d < 1) return false;
+    const bool leap = (y % 4 == 0 && y % 100 != 0) || y % 400 == 0;
+    // days in month: 31 except April, June, September, November (30) and February
+    const int64_t dim = mo == 2 ? (leap ? 29 : 28) : ((mo == 4 || mo == 6 || mo == 9 || mo == 11) ? 30 : 31);
+    if (d > dim || h > 23 || mi > 59 || se > 59) return false;
+    const int64_t t = (days_from_civil(y, mo, d) - origin) * 86400000 + h * 3600000 + mi * 60000 +
+                      se * 1000 + ms;
+    if (t < 0 || t >= (int64_t)kBadTs) return false;
+    ts = (uint32_t)t;
+    return true;
+}
+
+template <class Bytes>
+__device__ bool ipv4(const Bytes& b, uint64_t s, uint64_t e, uint32_t& a) {
+    uint32_t v = 0;
+    uint64_t i = s;
+    for (int part = 0; part < 4; ++part) {
+        uint32_t o = 0;
+        int nd = 0;
+        while (i < e && nd < 4) {
+            const uint32_t c = b[i] - '0';
+            if (c > 9u) break;
+            o = o * 10 + c;
+            ++nd;
+            ++i;
+        }
+        if (nd < 1 || nd > 3 || o > 255) return false;
+        v = (v << 8) | o;
+        if (part < 3) {
+            if (i >= e || b[i] != '.') return false;
+            ++i;
+        }
+    }
+    if (i != e) return false;
+    a = v;
+    return true;
+}
+
+template <class Bytes>
+__device__ bool count_u64(const Bytes& b, uint64_t s, uint64_t e, uint64_t& out) {
+    if (e <= s || e - s > 20) return false;
+    uint64_t v = 0;
+    for (uint64_t i = s; i < e; ++i) {
+        const uint32_t c = b[i] - '0';
+        if (c > 9u) return false;
+        if (v > (~0ull - c) / 10) return false;
+        v = v * 10 + c;
+    }
+    out = v;
+    return true;
+}
+
+// Parse the line [0, n) of b; false for a bad line.
+template <class Bytes>
+__device__ bool parse_line(const Bytes& b, uint64_t n, int64_t origin, uint32_t& ts, uint32_t& src,
+                           uint32_t& dst, uint64_t& nbytes) {
+    uint64_t s = 0;
+    for (int f = 1; f <= 21; ++f) {
+        uint64_t c = s;
+        while (c < n && b[c] != ',') ++c;
+        // field f is [s, c)
+        if (f == 1 && !capture_time(b, s, c, origin, ts)) return false;
+        if (f == 5 && !ipv4(b, s, c, src)) return false;
+        if (f == 8 && !ipv4(b, s, c, dst)) return false;
+        if (f == 21) return count_u64(b, s, c, nbytes);
+        if (c >= n) return false;  // the line ended before field 21
+        s = c + 1;
+    }
+    return false;
+}
+
+struct ParseArgs {
+    const uint8_t* text;
+    uint64_t len;
+    const uint64_t* starts;  // [n_nl + 1]
+    uint64_t n_nl;           // newlines
+    uint64_t n_lines;        // n_nl, + 1 for a last line without newline
+    int64_t origin;
+    uint32_t* ts;
+    uint32_t* src;
+    uint32_t* dst;
+    uint64_t* bytes;
+    unsigned long long* bad;
+};
+
+__global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes + 16];
+    for (uint64_t l0 = (uint64_t)blockIdx.x * kParseBlock; l0 < a.n_lines;
+         l0 += (uint64_t)gridDim.x * kParseBlock) {
+        const uint64_t l1 = l0 + kParseBlock < a.n_lines ? l0 + kParseBlock : a.n_lines;
+        // the group's bytes [g0, g1): from its first line's start to its last line's end
+        const uint64_t g0 = a.starts[l0];
+        const uint64_t g1 = l1 <= a.n_nl ? a.starts[l1] : a.len;
+        const uint64_t a0 = g0 & ~15ull;  // 16-byte aligned copy start
+        const bool in_lds = g1 - a0 <= kStageBytes;
+        if (in_lds) {
+            // coalesced copy of [a0, g1) into LDS (whole 16-byte groups when the
+            // text allows it, bytes at the ragged end)
+            const uint64_t full = (g1 - a0) / 16;
+            const bool vec = (((uintptr_t)a.text) & 15u) == 0;
+            for (uint64_t k = threadIdx.x; k < full; k += kParseBlock) {
+                if (vec) {
+                    *reinterpret_cast<uint4*>(stage + 16 * k) =
+                        *reinterpret_cast<const uint4*>(a.text + a0 + 16 * k);
+                } else {
+                    for (int q = 0; q < 16; ++q) stage[16 * k + q] = a.text[a0 + 16 * k + q];
+                }
+            }
+            for (uint64_t k = a0 + 16 * full + threadIdx.x; k < g1; k += kParseBlock)
+                stage[k - a0] = a.text[k];
+        }
+        __syncthreads();
+        const uint64_t l = l0 + threadIdx.x;
+        bool bad = false;
+        if (l < l1) {
+            const uint64_t s = a.starts[l];
+            const uint64_t e = l < a.n_nl ? a.starts[l + 1] - 1 : a.len;  // without the newline
+            uint32_t ts = 0, src = 0, dst = 0;
+            uint64_t nb = 0;
+            const LineBytes b{in_lds ? stage + (s - a0) : a.text + s};
+            if (!parse_line(b, e - s, a.origin, ts, src, dst, nb)) {
+                ts = kBadTs;
+                src = dst = 0;
+                nb = 0;
+                bad = true;
+            }
+            a.ts[l] = ts;
+            a.src[l] = src;
+            a.dst[l] = dst;
+            a.bytes[l] = nb;
+        }
+        const int n_bad = __syncthreads_count(bad ? 1 : 0);  // also ends the group's LDS use
+        if (threadIdx.x == 0 && n_bad) atomicAdd(a.bad, (unsigned long long)n_bad);
+    }
+}
+
+}  // namespace
+
+sinet_status parse_sessions(const uint8_t* text, uint64_t len, int64_t origin, const sinet_columns* out,
+                            uint64_t* n_lines, uint64_t* n_bad, hipStream_t s) {
+    *n_lines = 0;
+    *n_bad = 0;
+    if (len == 0) return SINET_OK;
+    const uint64_t n_blocks = (len + kScanBytes - 1) / kScanBytes;
+    if (n_blocks >= (1ull << 31)) return fail(SINET_ERR_UNSUPPORTED, "text above 2^47 bytes");
+    uint64_t* counts = nullptr;
+    unsigned long long* bad = nullptr;
+    uint64_t* starts = nullptr;
+    hipError_t e = hipMallocAsync((void**)&counts, 8 * (n_blocks + 1), s);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&bad, 8, s);
+    sinet_status st = check_hip(e, "parse workspace");
+    auto release = [&]() {
+        if (counts) (void)hipFreeAsync(counts, s);
+        if (bad) (void)hipFreeAsync(bad, s);
+        if (starts) (void)hipFreeAsync(starts, s);
+    };
+    if (st != SINET_OK) {
+        release();
+        return st;
+    }
+    const uint32_t vec = (((uintptr_t)text) & 15u) == 0 ? 1u : 0u;
+    hipLaunchKernelGGL(k_count_lines, dim3((unsigned)n_blocks), dim3(kParseBlock), 0, s, text, len,
+                       counts, vec);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, (uint32_t)n_blocks);
+    uint64_t n_nl = 0;
+    uint8_t last = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&n_nl, counts + n_blocks, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&last, text + len - 1, 1, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = check_hip(e, "parse line count");
+    if (st != SINET_OK) {
+        release();
+        return st;
+    }
+    const uint64_t lines = n_nl + (last != 10 ? 1 : 0);
+    *n_lines = lines;
+    if (lines > out->n) {
+        release();
+        return fail(SINET_ERR_INVALID_ARG, "output columns hold fewer sessions than the text has lines");
+    }
+    e = hipMallocAsync((void**)&starts, 8 * (n_nl + 1), s);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, 8, s);
+    st = check_hip(e, "parse workspace");
+    if (st == SINET_OK) {
+        hipLaunchKernelGGL(k_line_starts, dim3((unsigned)n_blocks), dim3(kParseBlock), 0, s, text, len,
+                           counts, starts, vec);
+        ParseArgs a{text, len, starts, n_nl, lines, origin,
+                    const_cast<uint32_t*>(out->ts), const_cast<uint32_t*>(out->src),
+                    const_cast<uint32_t*>(out->dst), const_cast<uint64_t*>(out->bytes), bad};
+        uint64_t grid = (lines + kParseBlock - 1) / kParseBlock;
+        const uint64_t cap = (uint64_t)device_cu_count() * 8;
+        if (grid > cap) grid = cap;
+        if (grid < 1) grid = 1;
+        hipLaunchKernelGGL(k_parse, dim3((unsigned)grid), dim3(kParseBlock), 0, s, a);
+        unsigned long long nb = 0;
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&nb, bad, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        st = check_hip(e, "parse");
+        *n_bad = nb;
+    }
+    release();
+    return st;
+}
+
+}  // namespace sinet
+
+extern "C" sinet_status sinet_parse_sessions(const uint8_t* text, uint64_t len, int32_t origin_days,
+                                             sinet_columns* out, uint64_t* n_lines, uint64_t* n_bad,
+                                             hipStream_t stream) {
+    using namespace sinet;
+    if (!out || !n_lines || !n_bad) return fail(SINET_ERR_INVALID_ARG, "NULL argument");
+    if (len && !text) return fail(SINET_ERR_INVALID_ARG, "text is NULL");
+    if (!out->ts || !out->src || !out->dst || !out->bytes)
+        return fail(SINET_ERR_INVALID_ARG, "output column is NULL");
+    return parse_sessions(text, len, origin_days, out, n_lines, n_bad, stream);
+}

@@ -213,6 +213,9 @@ sinet_status run_watch(const PassParams& p, uint32_t n_keys, int accumulate, hip
 // Coarser time frames: out[r][k] = sum of in[r][k * factor ..] (rebin.hip).
 sinet_status run_rebin(const uint64_t* in, uint64_t rows, uint64_t n_bins, uint32_t factor,
                        uint64_t* out, hipStream_t s);
+// Session text to columns (parse.hip); synchronous, sets the line counts.
+sinet_status parse_sessions(const uint8_t* text, uint64_t len, int64_t origin, const sinet_columns* out,
+                            uint64_t* n_lines, uint64_t* n_bad, hipStream_t s);
 sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s);
 sinet_status ws_free(void* ptr, hipStream_t s);
 uint32_t device_cu_count();

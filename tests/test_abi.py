@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
     names = _declared()
     for must in ("sinet_discriminate", "sinet_histogram", "sinet_pipeline", "sinet_table_create",
                  "sinet_table_train", "sinet_batch_plan_create", "sinet_batch_run",
-                 "sinet_autotune", "sinet_mlp_loss_grad", "sinet_watch_histogram"):
+                 "sinet_autotune", "sinet_mlp_loss_grad", "sinet_watch_histogram", "sinet_rebin",
+                 "sinet_parse_sessions", "sinet_streamer_pipeline"):
         assert must in names
 
 
