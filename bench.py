@@ -26,6 +26,7 @@ Forms timed on the same resident day (the first is the headline value):
                     [--forms plain,bsearch,...] [--no-cpu]
     python bench.py --host     the full day from host memory, streamed over PCIe
     python bench.py --rebin    the day's 1-ms histogram summed into one-hour frames
+    python bench.py --parse    a 4 GB chunk of session text parsed into columns
     python bench.py --watch    watch-list histograms over the full day
                                (two synthetic lists, 1,177 hosts, 10-min bins)
 """
@@ -49,12 +50,12 @@ DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched,batched_pla"
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
 COUNTER_TRAFFIC = {
-    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "b2ed44c0f83cd82c",
+    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "c3034047cd3d4bf3",
                  "bytes": 40.32e9},
-    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "b2ed44c0f83cd82c",
+    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "c3034047cd3d4bf3",
                  "bytes": 12.98e9},
     "k_watch": {"workload": "watch-fullday-1.6e+09-1177hosts-144x10min",
-                "kernels_sha": "b2ed44c0f83cd82c", "bytes": 14.77e9},
+                "kernels_sha": "c3034047cd3d4bf3", "bytes": 14.77e9},
 }
 KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")
 
@@ -74,6 +75,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--day-streams", type=int, default=24, help="streams of the batched day")
+    ap.add_argument("--parse", action="store_true",
+                    help="session text (Table 1 lines) parsed into columns, a 4 GB chunk")
     ap.add_argument("--rebin", action="store_true",
                     help="the day's millisecond histogram summed into one-hour frames")
     ap.add_argument("--host", action="store_true",
@@ -344,6 +347,57 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
     }
 
 
+def bench_parse(args, torch, sinet, sinetgen, gg):
+    """A 4 GB chunk of session text (the paper's chunks were 4, 6 and 9 GB of
+    PA-7080 records) parsed into columns: 500,000 generated Table 1 lines
+    (about 200 bytes each) repeated on the device to 20 million lines."""
+    import numpy as np
+    import oracle
+    from sinetgen import text as stext
+    wl = sinetgen.config(5)
+    i0 = wl.n // 2
+    unit = 500_000
+    buf, _ = stext.session_lines(wl, start=i0, stop=i0 + unit)
+    reps = 40
+    dev = torch.from_numpy(buf).cuda().repeat(reps)
+    n_lines = unit * reps
+    cols, bad = sinet.parse_sessions(dev, stext.ORIGIN_DAYS, capacity=n_lines)
+    torch.cuda.synchronize()
+    assert bad == 0 and cols["ts"].shape[0] == n_lines
+
+    def step():
+        sinet.parse_sessions(dev, stext.ORIGIN_DAYS, capacity=n_lines)
+
+    ms, ms_min, wall, _ = time_calls(torch, step, args.steps, args.warmup)
+    alg = dev.numel() + 20 * n_lines  # the text read once, the columns written once
+    achieved = alg / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "sessions/sec parsed from session text on 1 GPU, % HBM roofline",
+        "value": n_lines / (ms * 1e-3), "unit": "sessions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8 text",
+        "data": "synthetic (Table 1 lines generated from the full day's sessions, 500,000 lines "
+                f"repeated {reps} times)",
+        "config": {"workload": f"parse-{dev.numel() / 1e9:.1f}GB-{n_lines}lines",
+                   "text_bytes": dev.numel(), "lines": n_lines,
+                   "bytes_per_line": dev.numel() / n_lines, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "the parse call (count, scan, line starts, parse; synchronous)",
+                     "alg_bytes_per_launch": alg, "launch_ms": ms},
+        "forms": {"parse": {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall}},
+    }
+    if not args.no_cpu:
+        tc = time.perf_counter()
+        oracle.parse(buf, stext.ORIGIN_DAYS)
+        sec = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": unit / sec, "unit": "sessions/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the {unit} generated lines ({buf.shape[0] / 1e6:.0f} MB, "
+                                          f"{sec:.2f} s), parsed once"}
+    return line
+
+
 def bench_rebin(args, torch, sinet, sinetgen, gg):
     """The full day's millisecond histogram (4 x 86.4 M count and byte bins,
     5.53 GB) summed into 24 one-hour frames, as in the paper's Figures 6-7."""
@@ -541,6 +595,8 @@ def main():
         line = bench_host(args, torch, sinet, sinetgen, gg)
     elif args.rebin:
         line = bench_rebin(args, torch, sinet, sinetgen, gg)
+    elif args.parse:
+        line = bench_parse(args, torch, sinet, sinetgen, gg)
     elif args.config == 3:
         line = bench_batch(args, torch, sinet, sinetgen, gg)
     else:

@@ -14,8 +14,9 @@
 //   k_scan_counts  one workgroup: exclusive sums of the block counts;
 //   k_line_starts  every newline's position + 1 written at its line number;
 //   k_parse        a workgroup takes 256 consecutive lines, stages their bytes
-//                  in LDS with coalesced loads and each lane parses its line
-//                  from LDS (lines too long for LDS are read from device
+//                  in LDS with coalesced loads (as many whole lines at a time
+//                  as fit in 64 KB) and each lane parses its line from LDS
+//                  (a line longer than the staging is read from device
 //                  memory directly).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,7 +29,7 @@ namespace {
 
 constexpr int kParseBlock = 256;
 constexpr uint64_t kScanBytes = 64 * 1024;    // text bytes per counting block
-constexpr uint32_t kStageBytes = 48 * 1024;   // LDS staging of a workgroup's lines
+constexpr uint32_t kStageBytes = 64 * 1024;   // LDS staging of a workgroup's lines
 constexpr uint32_t kBadTs = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t nl_in(uint4 v) {
@@ -165,10 +166,42 @@ __device__ __forceinline__ int64_t days_from_civil(int64_t y, int64_t m, int64_t
     return era * 146097 + doe - 719468;
 }
 
-// Byte access to one line, from LDS or from device memory.
-struct LineBytes {
+// Byte access to one line staged in LDS.  comma(c, n) is the first ',' at
+// or after c, or n: it reads whole aligned 32-bit words and finds a comma
+// byte with the zero-byte test on (word ^ 0x2C2C2C2C); bytes of the word
+// before c are set to 0xFF first, so neither they nor a borrow out of them
+// can mark a byte.  Words may reach a few bytes past the line (or the staged
+// bytes: the staging array has 16 bytes of slack); positions at or past n
+// are not taken.
+struct LdsLine {
     const uint8_t* p;  // the line's first byte
     __device__ __forceinline__ uint32_t operator[](uint64_t i) const { return p[i]; }
+    __device__ __forceinline__ uint64_t comma(uint64_t c, uint64_t n) const {
+        for (uint64_t i = c; i < n;) {
+            const uint32_t off = (uint32_t)((uintptr_t)(p + i) & 3u);
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(p + i - off);
+            uint32_t x = w ^ 0x2C2C2C2Cu;
+            if (off) x |= 0xFFFFFFFFu >> (32 - 8 * off);
+            const uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;
+            if (z) {
+                const uint64_t at = i - off + (__builtin_ctz(z) >> 3);
+                return at < n ? at : n;
+            }
+            i += 4 - off;
+        }
+        return n;
+    }
+};
+
+// Byte access to one line in device memory (lines too long for the staging):
+// bytes only, never past the line.
+struct GlobalLine {
+    const uint8_t* p;
+    __device__ __forceinline__ uint32_t operator[](uint64_t i) const { return p[i]; }
+    __device__ __forceinline__ uint64_t comma(uint64_t c, uint64_t n) const {
+        while (c < n && p[c] != ',') ++c;
+        return c;
+    }
 };
 
 template <class Bytes>
@@ -184,7 +217,7 @@ __device__ __forceinline__ bool dec(const Bytes& b, uint64_t at, int n, int64_t&
 }
 
 template <class Bytes>
-__device__ bool capture_time(const Bytes& b, uint64_t s, uint64_t e, int64_t origin, uint32_t& ts) {
+__device__ __forceinline__ bool capture_time(const Bytes& b, uint64_t s, uint64_t e, int64_t origin, uint32_t& ts) {
     if (e - s != 23) return false;
     if (b[s + 4] != '/' || b[s + 7] != '/' || b[s + 10] != ' ' || b[s + 13] != ':' ||
         b[s + 16] != ':' || b[s + 19] != '.')
@@ -206,7 +239,7 @@ __device__ bool capture_time(const Bytes& b, uint64_t s, uint64_t e, int64_t ori
 }
 
 template <class Bytes>
-__device__ bool ipv4(const Bytes& b, uint64_t s, uint64_t e, uint32_t& a) {
+__device__ __forceinline__ bool ipv4(const Bytes& b, uint64_t s, uint64_t e, uint32_t& a) {
     uint32_t v = 0;
     uint64_t i = s;
     for (int part = 0; part < 4; ++part) {
@@ -232,7 +265,7 @@ __device__ bool ipv4(const Bytes& b, uint64_t s, uint64_t e, uint32_t& a) {
 }
 
 template <class Bytes>
-__device__ bool count_u64(const Bytes& b, uint64_t s, uint64_t e, uint64_t& out) {
+__device__ __forceinline__ bool count_u64(const Bytes& b, uint64_t s, uint64_t e, uint64_t& out) {
     if (e <= s || e - s > 20) return false;
     uint64_t v = 0;
     for (uint64_t i = s; i < e; ++i) {
@@ -247,12 +280,11 @@ __device__ bool count_u64(const Bytes& b, uint64_t s, uint64_t e, uint64_t& out)
 
 // Parse the line [0, n) of b; false for a bad line.
 template <class Bytes>
-__device__ bool parse_line(const Bytes& b, uint64_t n, int64_t origin, uint32_t& ts, uint32_t& src,
+__device__ __forceinline__ bool parse_line(const Bytes& b, uint64_t n, int64_t origin, uint32_t& ts, uint32_t& src,
                            uint32_t& dst, uint64_t& nbytes) {
     uint64_t s = 0;
     for (int f = 1; f <= 21; ++f) {
-        uint64_t c = s;
-        while (c < n && b[c] != ',') ++c;
+        const uint64_t c = b.comma(s, n);
         // field f is [s, c)
         if (f == 1 && !capture_time(b, s, c, origin, ts)) return false;
         if (f == 5 && !ipv4(b, s, c, src)) return false;
@@ -283,48 +315,73 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
     for (uint64_t l0 = (uint64_t)blockIdx.x * kParseBlock; l0 < a.n_lines;
          l0 += (uint64_t)gridDim.x * kParseBlock) {
         const uint64_t l1 = l0 + kParseBlock < a.n_lines ? l0 + kParseBlock : a.n_lines;
-        // the group's bytes [g0, g1): from its first line's start to its last line's end
-        const uint64_t g0 = a.starts[l0];
-        const uint64_t g1 = l1 <= a.n_nl ? a.starts[l1] : a.len;
-        const uint64_t a0 = g0 & ~15ull;  // 16-byte aligned copy start
-        const bool in_lds = g1 - a0 <= kStageBytes;
-        if (in_lds) {
-            // coalesced copy of [a0, g1) into LDS (whole 16-byte groups when the
-            // text allows it, bytes at the ragged end)
+        const uint64_t l = l0 + threadIdx.x;
+        // this lane's line [s, e) (without its newline) and the end of its bytes
+        uint64_t s = 0, e = 0, g = 0;
+        if (l < l1) {
+            s = a.starts[l];
+            g = l < a.n_nl ? a.starts[l + 1] : a.len;
+            e = l < a.n_nl ? g - 1 : a.len;
+        }
+        uint32_t ts = kBadTs, src = 0, dst = 0;
+        uint64_t nb = 0;
+        bool ok = false;
+        // lines [next, l1) are left; each step stages the longest prefix of
+        // them whose bytes fit in LDS (line ends grow with l, so the lanes
+        // that fit are a prefix), or parses one line too long for the
+        // staging from device memory
+        for (uint64_t next = l0; next < l1;) {
+            const uint64_t a0 = a.starts[next] & ~15ull;  // 16-byte aligned copy start
+            const bool fits = l >= next && l < l1 && g - a0 <= kStageBytes;
+            const uint64_t n_fit = (uint64_t)__syncthreads_count(fits ? 1 : 0);
+            if (n_fit == 0) {
+                if (l == next)
+                    ok = parse_line(GlobalLine{a.text + s}, e - s, a.origin, ts, src, dst, nb);
+                next += 1;
+                continue;
+            }
+            const uint64_t m = next + n_fit;  // lines [next, m) are staged
+            const uint64_t g1 = m <= a.n_nl ? a.starts[m] : a.len;
             const uint64_t full = (g1 - a0) / 16;
-            const bool vec = (((uintptr_t)a.text) & 15u) == 0;
-            for (uint64_t k = threadIdx.x; k < full; k += kParseBlock) {
-                if (vec) {
-                    *reinterpret_cast<uint4*>(stage + 16 * k) =
-                        *reinterpret_cast<const uint4*>(a.text + a0 + 16 * k);
-                } else {
-                    for (int q = 0; q < 16; ++q) stage[16 * k + q] = a.text[a0 + 16 * k + q];
+            if ((((uintptr_t)a.text) & 15u) == 0) {
+                // four 16-byte loads of the lane in flight before its LDS writes
+                const uint4* src4 = reinterpret_cast<const uint4*>(a.text + a0);
+                uint4* dst4 = reinterpret_cast<uint4*>(stage);
+                for (uint64_t k = threadIdx.x; k < full; k += 4 * kParseBlock) {
+                    const uint64_t q1 = k + kParseBlock, q2 = k + 2 * kParseBlock,
+                                   q3 = k + 3 * kParseBlock;
+                    const uint4 r0 = src4[k];
+                    const uint4 r1 = q1 < full ? src4[q1] : r0;
+                    const uint4 r2 = q2 < full ? src4[q2] : r0;
+                    const uint4 r3 = q3 < full ? src4[q3] : r0;
+                    dst4[k] = r0;
+                    if (q1 < full) dst4[q1] = r1;
+                    if (q2 < full) dst4[q2] = r2;
+                    if (q3 < full) dst4[q3] = r3;
                 }
+            } else {
+                for (uint64_t k = threadIdx.x; k < 16 * full; k += kParseBlock) stage[k] = a.text[a0 + k];
             }
             for (uint64_t k = a0 + 16 * full + threadIdx.x; k < g1; k += kParseBlock)
                 stage[k - a0] = a.text[k];
+            __syncthreads();
+            if (l >= next && l < m)
+                ok = parse_line(LdsLine{stage + (s - a0)}, e - s, a.origin, ts, src, dst, nb);
+            __syncthreads();  // the staging is free for the next step
+            next = m;
         }
-        __syncthreads();
-        const uint64_t l = l0 + threadIdx.x;
-        bool bad = false;
         if (l < l1) {
-            const uint64_t s = a.starts[l];
-            const uint64_t e = l < a.n_nl ? a.starts[l + 1] - 1 : a.len;  // without the newline
-            uint32_t ts = 0, src = 0, dst = 0;
-            uint64_t nb = 0;
-            const LineBytes b{in_lds ? stage + (s - a0) : a.text + s};
-            if (!parse_line(b, e - s, a.origin, ts, src, dst, nb)) {
+            if (!ok) {
                 ts = kBadTs;
                 src = dst = 0;
                 nb = 0;
-                bad = true;
             }
             a.ts[l] = ts;
             a.src[l] = src;
             a.dst[l] = dst;
             a.bytes[l] = nb;
         }
-        const int n_bad = __syncthreads_count(bad ? 1 : 0);  // also ends the group's LDS use
+        const int n_bad = __syncthreads_count(l < l1 && !ok ? 1 : 0);
         if (threadIdx.x == 0 && n_bad) atomicAdd(a.bad, (unsigned long long)n_bad);
     }
 }
