@@ -335,7 +335,8 @@ sinet_status sinet_batch_plan_destroy(sinet_batch_plan* plan);
  *   src   field 5, dst field 8: dotted quads of 1-3 digit octets <= 255;
  *   bytes field 21: 1-20 decimal digits, at most 2^64 - 1.
  * A line with fewer than 21 fields or a malformed one of these fields gives
- * ts = 0xFFFFFFFF (outside every window), src = dst = bytes = 0, and counts
+ * ts = 0xFFFFFFFF (no valid line has it; outside any window ending before
+ * 2^32 - 1 ms), src = dst = bytes = 0, and counts
  * in *n_bad.  *n_lines receives the number of lines.  The kernels read whole
  * aligned 16-byte groups of text and stay inside [text, text + len).
  * Errors: INVALID_ARG (NULL pointer, more lines than out->n: *n_lines then
