@@ -156,13 +156,14 @@ __global__ void __launch_bounds__(kParseBlock) k_line_starts(const uint8_t* __re
 
 // days since 1970-01-01 of a proleptic Gregorian date (H. Hinnant's
 // days_from_civil)
-__device__ __forceinline__ int64_t days_from_civil(int64_t y, int64_t m, int64_t d) {
+// (years 0..9999 here: 32-bit arithmetic suffices)
+__device__ __forceinline__ int32_t days_from_civil(int32_t y, int32_t m, int32_t d) {
     y -= m <= 2 ? 1 : 0;
-    const int64_t era = (y >= 0 ? y : y - 399) / 400;
-    const int64_t yoe = y - era * 400;
-    const int64_t mp = m > 2 ? m - 3 : m + 9;
-    const int64_t doy = (153 * mp + 2) / 5 + d - 1;
-    const int64_t doe = yoe * 365 + yoe / 4 - yoe / 100 + doy;
+    const int32_t era = (y >= 0 ? y : y - 399) / 400;
+    const int32_t yoe = y - era * 400;
+    const int32_t mp = m > 2 ? m - 3 : m + 9;
+    const int32_t doy = (153 * mp + 2) / 5 + d - 1;
+    const int32_t doe = yoe * 365 + yoe / 4 - yoe / 100 + doy;
     return era * 146097 + doe - 719468;
 }
 
@@ -205,8 +206,8 @@ struct GlobalLine {
 };
 
 template <class Bytes>
-__device__ __forceinline__ bool dec(const Bytes& b, uint64_t at, int n, int64_t& v) {
-    int64_t x = 0;
+__device__ __forceinline__ bool dec(const Bytes& b, uint64_t at, int n, int32_t& v) {
+    int32_t x = 0;
     for (int i = 0; i < n; ++i) {
         const uint32_t c = b[at + i] - '0';
         if (c > 9u) return false;
@@ -222,17 +223,17 @@ __device__ __forceinline__ bool capture_time(const Bytes& b, uint64_t s, uint64_
     if (b[s + 4] != '/' || b[s + 7] != '/' || b[s + 10] != ' ' || b[s + 13] != ':' ||
         b[s + 16] != ':' || b[s + 19] != '.')
         return false;
-    int64_t y, mo, d, h, mi, se, ms;
+    int32_t y, mo, d, h, mi, se, ms;
     if (!dec(b, s, 4, y) || !dec(b, s + 5, 2, mo) || !dec(b, s + 8, 2, d) || !dec(b, s + 11, 2, h) ||
         !dec(b, s + 14, 2, mi) || !dec(b, s + 17, 2, se) || !dec(b, s + 20, 3, ms))
         return false;
     if (mo < 1 || mo > 12 || d < 1) return false;
     const bool leap = (y % 4 == 0 && y % 100 != 0) || y % 400 == 0;
     // days in month: 31 except April, June, September, November (30) and February
-    const int64_t dim = mo == 2 ? (leap ? 29 : 28) : ((mo == 4 || mo == 6 || mo == 9 || mo == 11) ? 30 : 31);
+    const int32_t dim = mo == 2 ? (leap ? 29 : 28) : ((mo == 4 || mo == 6 || mo == 9 || mo == 11) ? 30 : 31);
     if (d > dim || h > 23 || mi > 59 || se > 59) return false;
-    const int64_t t = (days_from_civil(y, mo, d) - origin) * 86400000 + h * 3600000 + mi * 60000 +
-                      se * 1000 + ms;
+    const int64_t t = ((int64_t)days_from_civil(y, mo, d) - origin) * 86400000 + h * 3600000 +
+                      mi * 60000 + se * 1000 + ms;
     if (t < 0 || t >= (int64_t)kBadTs) return false;
     ts = (uint32_t)t;
     return true;
@@ -312,6 +313,7 @@ struct ParseArgs {
 
 __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes + 16];
+    __shared__ uint64_t s_start[kParseBlock], s_end[kParseBlock];  // the group's line bytes
     for (uint64_t l0 = (uint64_t)blockIdx.x * kParseBlock; l0 < a.n_lines;
          l0 += (uint64_t)gridDim.x * kParseBlock) {
         const uint64_t l1 = l0 + kParseBlock < a.n_lines ? l0 + kParseBlock : a.n_lines;
@@ -323,6 +325,8 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
             g = l < a.n_nl ? a.starts[l + 1] : a.len;
             e = l < a.n_nl ? g - 1 : a.len;
         }
+        s_start[threadIdx.x] = s;
+        s_end[threadIdx.x] = g;  // read after the first barrier below
         uint32_t ts = kBadTs, src = 0, dst = 0;
         uint64_t nb = 0;
         bool ok = false;
@@ -330,8 +334,9 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
         // them whose bytes fit in LDS (line ends grow with l, so the lanes
         // that fit are a prefix), or parses one line too long for the
         // staging from device memory
+        __syncthreads();
         for (uint64_t next = l0; next < l1;) {
-            const uint64_t a0 = a.starts[next] & ~15ull;  // 16-byte aligned copy start
+            const uint64_t a0 = s_start[next - l0] & ~15ull;  // 16-byte aligned copy start
             const bool fits = l >= next && l < l1 && g - a0 <= kStageBytes;
             const uint64_t n_fit = (uint64_t)__syncthreads_count(fits ? 1 : 0);
             if (n_fit == 0) {
@@ -341,7 +346,7 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
                 continue;
             }
             const uint64_t m = next + n_fit;  // lines [next, m) are staged
-            const uint64_t g1 = m <= a.n_nl ? a.starts[m] : a.len;
+            const uint64_t g1 = s_end[m - 1 - l0];
             const uint64_t full = (g1 - a0) / 16;
             if ((((uintptr_t)a.text) & 15u) == 0) {
                 // four 16-byte loads of the lane in flight before its LDS writes
@@ -381,6 +386,7 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
             a.dst[l] = dst;
             a.bytes[l] = nb;
         }
+        // also keeps s_start / s_end until every lane is past the group
         const int n_bad = __syncthreads_count(l < l1 && !ok ? 1 : 0);
         if (threadIdx.x == 0 && n_bad) atomicAdd(a.bad, (unsigned long long)n_bad);
     }

@@ -36,7 +36,7 @@ def torch():
 
 
 def _dev_text(torch, buf):
-    return torch.from_numpy(np.ascontiguousarray(buf, dtype=np.uint8)).cuda()
+    return torch.from_numpy(np.array(buf, dtype=np.uint8)).cuda()  # a writable host copy
 
 
 def _check(sinet, torch, buf, origin, off=0):
