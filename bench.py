@@ -479,7 +479,7 @@ def bench_host(args, torch, sinet, sinetgen, gg):
     page = {c: v.numpy().copy() for c, v in pin.items()}
     lab_np = np.empty(wl.n, np.uint8)
     ms_page = run(page, lab_np)
-    moved = 20 * wl.n + wl.n  # columns in, labels out
+    moved = 20 * wl.n  # columns in (the labels go the other way on the full-duplex link)
     achieved = moved / (ms_pin * 1e-3) / 1e9
     st.close()
     return {
@@ -492,7 +492,7 @@ def bench_host(args, torch, sinet, sinetgen, gg):
                    "form": "streamed from host", "parallelism": "single GPU"},
         "roofline": {"bound": "host link", "achieved": achieved, "peak": h2d, "unit": "GB/s",
                      "frac": achieved / h2d, "traffic": None,
-                     "kernel": "host-to-device copies of the columns, labels back",
+                     "kernel": "host-to-device copies of the columns (labels back concurrently)",
                      "peak_note": "measured pinned host-to-device copy rate on this box"},
         "forms": {"pinned": {"ms_per_step": ms_pin, "sessions_per_s": wl.n / (ms_pin * 1e-3)},
                   "pageable": {"ms_per_step": ms_page,

@@ -363,7 +363,7 @@ sinet_status sinet_rebin(const uint64_t* in, uint32_t rows, uint32_t n_bins, uin
  * Table 3 runs out of device memory on large inputs).  A streamer owns two
  * staging slots, each with device buffers and pinned host buffers for
  * chunk_sessions sessions (about 42 bytes per session per slot), and its own
- * copy stream (default priority).  Errors: INVALID_ARG (chunk_sessions 0 or
+ * copy stream (default priority, non-blocking).  Errors: INVALID_ARG (chunk_sessions 0 or
  * above 2^31), OUT_OF_MEMORY.  Synchronous. */
 typedef struct sinet_streamer sinet_streamer;
 sinet_status sinet_streamer_create(uint64_t chunk_sessions, sinet_streamer** out);

@@ -115,7 +115,9 @@ sinet_status sinet_streamer_create(uint64_t chunk_sessions, sinet_streamer** out
     s->chunk = chunk_sessions;
     (void)hipGetDevice(&s->device);
     const uint64_t c = chunk_sessions;
-    hipError_t e = hipStreamCreate(&s->copy);  // default priority
+    // default priority; non-blocking, so it never waits for work on the null
+    // stream implicitly (the events between the streams order everything)
+    hipError_t e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
     for (Slot& x : s->slot) {
         if (e == hipSuccess) e = hipMalloc((void**)&x.d_ts, 4 * c);
         if (e == hipSuccess) e = hipMalloc((void**)&x.d_src, 4 * c);
