@@ -1751,6 +1751,22 @@ __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
         cs = gload4(p.src + g * 4);
         cd = gload4(p.dst + g * 4);
     }
+    // a group's matches are added one iteration later, so the loads of their
+    // times and byte counts overlap the next group's lookups
+    uint32_t pcode[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint4 pt = make_uint4(0, 0, 0, 0);
+    ulonglong2 pb01 = make_ulonglong2(0, 0), pb23 = pb01;
+    bool pend = false;
+    auto apply = [&]() {
+        if (!pend) return;
+        const uint32_t ts[4] = {pt.x, pt.y, pt.z, pt.w};
+        const uint64_t by[4] = {pb01.x, pb01.y, pb23.x, pb23.y};
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (pcode[q])
+                watch_add<PRIV>(w, hc, hb, q >> 2, pcode[q], lkey != nullptr, ts[q & 3], by[q & 3], d);
+        pend = false;
+    };
     for (; g < groups; g += stride) {
         const uint64_t i = g * 4;
         uint4 ns = cs, nd = cd;
@@ -1767,18 +1783,17 @@ __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
             uint32_t any = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) any |= code[q];
+            apply();  // the previous group's, its loads issued an iteration ago
             if (any) {
-                const uint4 t4 = gload4(p.ts + i);
-                const ulonglong2 b01 = gload2(p.bytes + i), b23 = gload2(p.bytes + i + 2);
-                const uint32_t ts[4] = {t4.x, t4.y, t4.z, t4.w};
-                const uint64_t by[4] = {b01.x, b01.y, b23.x, b23.y};
+                pt = gload4(p.ts + i);
+                pb01 = gload2(p.bytes + i);
+                pb23 = gload2(p.bytes + i + 2);
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (code[q])
-                        watch_add<PRIV>(w, hc, hb, q >> 2, code[q], lkey != nullptr, ts[q & 3],
-                                        by[q & 3], d);
+                for (int q = 0; q < 8; ++q) pcode[q] = code[q];
+                pend = true;
             }
         } else {
+            apply();
             for (uint64_t e = i; e < p.n && e < i + 4; ++e) {
                 const uint32_t a[2] = {*glob(p.src + e), *glob(p.dst + e)};
                 uint32_t code[2];
@@ -1794,6 +1809,7 @@ __global__ void __launch_bounds__(kWatchBlock) k_watch(WatchParams w) {
         cs = ns;
         cd = nd;
     }
+    apply();
     d.flush(p.dropped);
     if constexpr (PRIV) {
         __syncthreads();
