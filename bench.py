@@ -50,12 +50,12 @@ DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched,batched_pla"
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
 COUNTER_TRAFFIC = {
-    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "c3034047cd3d4bf3",
+    "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "7b136c4cdca9f0c5",
                  "bytes": 40.32e9},
-    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "c3034047cd3d4bf3",
+    "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "7b136c4cdca9f0c5",
                  "bytes": 12.98e9},
     "k_watch": {"workload": "watch-fullday-1.6e+09-1177hosts-144x10min",
-                "kernels_sha": "c3034047cd3d4bf3", "bytes": 14.77e9},
+                "kernels_sha": "7b136c4cdca9f0c5", "bytes": 14.77e9},
 }
 KERNEL_SOURCES = ("kernels.hip", "sinet_internal.h", "sinet_device.h", "inout_index.h")
 
