@@ -73,6 +73,17 @@ def test_host_side_argument_errors():
     assert lib.sinet_discriminate(None, P(16), P(16), 4, P(16), None, None, None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_watch_histogram(None, ctypes.byref(cols), ctypes.byref(w), 3, ctypes.byref(h), 0,
                                      None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_rebin(None, 4, 10, 2, P(16), None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_rebin(P(16), 4, 10, 0, P(16), None) == sinet.ERR_INVALID_ARG
+    n_lines, n_bad = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    assert lib.sinet_parse_sessions(P(16), 10, 0, None, ctypes.byref(n_lines), ctypes.byref(n_bad),
+                                    None) == sinet.ERR_INVALID_ARG
+    empty_cols = sinet.Columns(None, None, None, None, 4)
+    assert lib.sinet_parse_sessions(P(16), 10, 0, ctypes.byref(empty_cols), ctypes.byref(n_lines),
+                                    ctypes.byref(n_bad), None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_streamer_create(0, ctypes.byref(out)) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_streamer_create((1 << 31) + 1, ctypes.byref(out)) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_streamer_pipeline(None, None, None, None, None, None, 0, None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_mlp_loss_grad(None, P(16), P(16), 4, P(16), P(16), None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_batch_plan_create(None, 0, None, None, ctypes.byref(out)) != sinet.OK
     assert lib.sinet_status_string(2) == b"out of device memory"
