@@ -176,16 +176,16 @@ __device__ __forceinline__ int32_t days_from_civil(int32_t y, int32_t m, int32_t
 // are not taken.
 struct LdsLine {
     const uint8_t* p;  // the line's first byte
-    __device__ __forceinline__ uint32_t operator[](uint64_t i) const { return p[i]; }
-    __device__ __forceinline__ uint64_t comma(uint64_t c, uint64_t n) const {
-        for (uint64_t i = c; i < n;) {
+    __device__ __forceinline__ uint32_t operator[](uint32_t i) const { return p[i]; }
+    __device__ __forceinline__ uint32_t comma(uint32_t c, uint32_t n) const {
+        for (uint32_t i = c; i < n;) {
             const uint32_t off = (uint32_t)((uintptr_t)(p + i) & 3u);
             const uint32_t w = *reinterpret_cast<const uint32_t*>(p + i - off);
             uint32_t x = w ^ 0x2C2C2C2Cu;
             if (off) x |= 0xFFFFFFFFu >> (32 - 8 * off);
             const uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;
             if (z) {
-                const uint64_t at = i - off + (__builtin_ctz(z) >> 3);
+                const uint32_t at = i - off + (__builtin_ctz(z) >> 3);
                 return at < n ? at : n;
             }
             i += 4 - off;
@@ -198,15 +198,15 @@ struct LdsLine {
 // bytes only, never past the line.
 struct GlobalLine {
     const uint8_t* p;
-    __device__ __forceinline__ uint32_t operator[](uint64_t i) const { return p[i]; }
-    __device__ __forceinline__ uint64_t comma(uint64_t c, uint64_t n) const {
+    __device__ __forceinline__ uint32_t operator[](uint32_t i) const { return p[i]; }
+    __device__ __forceinline__ uint32_t comma(uint32_t c, uint32_t n) const {
         while (c < n && p[c] != ',') ++c;
         return c;
     }
 };
 
 template <class Bytes>
-__device__ __forceinline__ bool dec(const Bytes& b, uint64_t at, int n, int32_t& v) {
+__device__ __forceinline__ bool dec(const Bytes& b, uint32_t at, int n, int32_t& v) {
     int32_t x = 0;
     for (int i = 0; i < n; ++i) {
         const uint32_t c = b[at + i] - '0';
@@ -218,7 +218,7 @@ __device__ __forceinline__ bool dec(const Bytes& b, uint64_t at, int n, int32_t&
 }
 
 template <class Bytes>
-__device__ __forceinline__ bool capture_time(const Bytes& b, uint64_t s, uint64_t e, int64_t origin, uint32_t& ts) {
+__device__ __forceinline__ bool capture_time(const Bytes& b, uint32_t s, uint32_t e, int64_t origin, uint32_t& ts) {
     if (e - s != 23) return false;
     if (b[s + 4] != '/' || b[s + 7] != '/' || b[s + 10] != ' ' || b[s + 13] != ':' ||
         b[s + 16] != ':' || b[s + 19] != '.')
@@ -240,9 +240,9 @@ __device__ __forceinline__ bool capture_time(const Bytes& b, uint64_t s, uint64_
 }
 
 template <class Bytes>
-__device__ __forceinline__ bool ipv4(const Bytes& b, uint64_t s, uint64_t e, uint32_t& a) {
+__device__ __forceinline__ bool ipv4(const Bytes& b, uint32_t s, uint32_t e, uint32_t& a) {
     uint32_t v = 0;
-    uint64_t i = s;
+    uint32_t i = s;
     for (int part = 0; part < 4; ++part) {
         uint32_t o = 0;
         int nd = 0;
@@ -266,13 +266,15 @@ __device__ __forceinline__ bool ipv4(const Bytes& b, uint64_t s, uint64_t e, uin
 }
 
 template <class Bytes>
-__device__ __forceinline__ bool count_u64(const Bytes& b, uint64_t s, uint64_t e, uint64_t& out) {
+__device__ __forceinline__ bool count_u64(const Bytes& b, uint32_t s, uint32_t e, uint64_t& out) {
     if (e <= s || e - s > 20) return false;
     uint64_t v = 0;
-    for (uint64_t i = s; i < e; ++i) {
+    for (uint32_t i = s; i < e; ++i) {
         const uint32_t c = b[i] - '0';
         if (c > 9u) return false;
-        if (v > (~0ull - c) / 10) return false;
+        // v * 10 + c > 2^64 - 1 = 18446744073709551615 exactly when v exceeds
+        // floor((2^64 - 1) / 10), or equals it and c > 5
+        if (v > 1844674407370955161ull || (v == 1844674407370955161ull && c > 5u)) return false;
         v = v * 10 + c;
     }
     out = v;
@@ -281,11 +283,11 @@ __device__ __forceinline__ bool count_u64(const Bytes& b, uint64_t s, uint64_t e
 
 // Parse the line [0, n) of b; false for a bad line.
 template <class Bytes>
-__device__ __forceinline__ bool parse_line(const Bytes& b, uint64_t n, int64_t origin, uint32_t& ts, uint32_t& src,
+__device__ __forceinline__ bool parse_line(const Bytes& b, uint32_t n, int64_t origin, uint32_t& ts, uint32_t& src,
                            uint32_t& dst, uint64_t& nbytes) {
-    uint64_t s = 0;
+    uint32_t s = 0;
     for (int f = 1; f <= 21; ++f) {
-        const uint64_t c = b.comma(s, n);
+        const uint32_t c = b.comma(s, n);
         // field f is [s, c)
         if (f == 1 && !capture_time(b, s, c, origin, ts)) return false;
         if (f == 5 && !ipv4(b, s, c, src)) return false;
@@ -340,8 +342,8 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
             const bool fits = l >= next && l < l1 && g - a0 <= kStageBytes;
             const uint64_t n_fit = (uint64_t)__syncthreads_count(fits ? 1 : 0);
             if (n_fit == 0) {
-                if (l == next)
-                    ok = parse_line(GlobalLine{a.text + s}, e - s, a.origin, ts, src, dst, nb);
+                if (l == next && e - s < 0xFFFFFFFFull)  // longer lines are bad
+                    ok = parse_line(GlobalLine{a.text + s}, (uint32_t)(e - s), a.origin, ts, src, dst, nb);
                 next += 1;
                 continue;
             }
@@ -371,7 +373,7 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
                 stage[k - a0] = a.text[k];
             __syncthreads();
             if (l >= next && l < m)
-                ok = parse_line(LdsLine{stage + (s - a0)}, e - s, a.origin, ts, src, dst, nb);
+                ok = parse_line(LdsLine{stage + (s - a0)}, (uint32_t)(e - s), a.origin, ts, src, dst, nb);
             __syncthreads();  // the staging is free for the next step
             next = m;
         }
