@@ -1,4 +1,6 @@
-"""CPU oracle for discrimination and millisecond histogramming.
+"""CPU oracle for discrimination and millisecond histogramming, and for the
+watch-list histograms, coarser time frames and session-text parsing beside
+them.
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the GPU library never does, and this
