@@ -351,8 +351,6 @@ def bench_parse(args, torch, sinet, sinetgen, gg):
     """A 4 GB chunk of session text (the paper's chunks were 4, 6 and 9 GB of
     PA-7080 records) parsed into columns: 500,000 generated Table 1 lines
     (about 200 bytes each) repeated on the device to 20 million lines."""
-    import numpy as np
-    import oracle
     from sinetgen import text as stext
     wl = sinetgen.config(5)
     i0 = wl.n // 2
@@ -388,6 +386,7 @@ def bench_parse(args, torch, sinet, sinetgen, gg):
         "forms": {"parse": {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall}},
     }
     if not args.no_cpu:
+        import oracle
         tc = time.perf_counter()
         oracle.parse(buf, stext.ORIGIN_DAYS)
         sec = time.perf_counter() - tc
