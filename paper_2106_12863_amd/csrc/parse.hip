@@ -299,6 +299,44 @@ __device__ __forceinline__ bool parse_line(const Bytes& b, uint32_t n, int64_t o
     return false;
 }
 
+// parse_line for a line staged in LDS: one pass over the line's aligned
+// 32-bit words finds the commas that bound fields 1, 5, 8 and 21 (an exact
+// per-byte zero test on word ^ 0x2C2C2C2C marks every comma of a word; bytes
+// outside the line are set to 0xFF first), so every lane runs the same loop
+// over words instead of one search per field.  Same rules as parse_line.
+__device__ __forceinline__ bool parse_line_lds(const uint8_t* p, uint32_t n, int64_t origin,
+                                               uint32_t& ts, uint32_t& src, uint32_t& dst,
+                                               uint64_t& nbytes) {
+    const uint32_t off = (uint32_t)((uintptr_t)p & 3u);
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(p - off);
+    // positions of commas 1, 4, 5, 7, 8, 20 and 21 (field f is [comma f-1 + 1, comma f))
+    uint32_t c1 = 0, c4 = 0, c5 = 0, c7 = 0, c8 = 0, c20 = 0, c21 = n;
+    uint32_t k = 0;  // commas seen
+    for (uint32_t j = 0; 4 * j < n + off && k < 21; ++j) {
+        uint32_t x = w[j] ^ 0x2C2C2C2Cu;
+        if (j == 0 && off) x |= 0xFFFFFFFFu >> (32 - 8 * off);  // bytes before the line
+        const uint32_t hi = n + off - 4 * j;                      // bytes at or past n
+        if (hi < 4) x |= 0xFFFFFFFFu << (8 * hi);
+        uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 per comma
+        while (z && k < 21) {
+            const uint32_t at = 4 * j + ((uint32_t)__builtin_ctz(z) >> 3) - off;
+            ++k;
+            if (k == 1) c1 = at;
+            if (k == 4) c4 = at;
+            if (k == 5) c5 = at;
+            if (k == 7) c7 = at;
+            if (k == 8) c8 = at;
+            if (k == 20) c20 = at;
+            if (k == 21) c21 = at;
+            z &= z - 1;
+        }
+    }
+    if (k < 20) return false;  // fewer than 21 fields
+    const LdsLine b{p};
+    return capture_time(b, 0u, c1, origin, ts) && ipv4(b, c4 + 1, c5, src) &&
+           ipv4(b, c7 + 1, c8, dst) && count_u64(b, c20 + 1, c21, nbytes);
+}
+
 struct ParseArgs {
     const uint8_t* text;
     uint64_t len;
@@ -373,7 +411,7 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
                 stage[k - a0] = a.text[k];
             __syncthreads();
             if (l >= next && l < m)
-                ok = parse_line(LdsLine{stage + (s - a0)}, (uint32_t)(e - s), a.origin, ts, src, dst, nb);
+                ok = parse_line_lds(stage + (s - a0), (uint32_t)(e - s), a.origin, ts, src, dst, nb);
             __syncthreads();  // the staging is free for the next step
             next = m;
         }
