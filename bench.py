@@ -571,7 +571,7 @@ def bench_watch(args, torch, sinet, sinetgen, gg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if args.copy_gb:
