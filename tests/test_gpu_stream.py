@@ -105,3 +105,26 @@ def test_streamer_small_chunks_and_edges(sinet, torch):
     with pytest.raises(ValueError):
         st.pipeline(tab, s["ts"], s["src"][:10], s["dst"], s["bytes"], t0, w, nb)
     st.close()
+
+
+@pytest.mark.parametrize("kind", ["trie", "pla"])
+def test_streamed_with_separate_lookup_pass(sinet, torch, kind):
+    """Tables whose lookups run as their own pass (trie, learned) stream the
+    same way: equal to the resident call, with and without host labels."""
+    wl = sinetgen.config(4, n=1_000_003)
+    s = sinetgen.sessions(wl)
+    tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=False)
+    if kind == "pla":
+        tab.train()
+    w = wl.window
+    lab_r, hist_r = _resident(sinet, tab, s, w.t0, w.width, w.n_bins)
+    st = sinet.Streamer(chunk=300_007)
+    for label in (True, None):
+        lab, hist = st.pipeline(tab, s["ts"], s["src"], s["dst"], s["bytes"], w.t0, w.width, w.n_bins,
+                                label=label)
+        torch.cuda.synchronize()
+        if label is True:
+            assert np.array_equal(lab, lab_r.cpu().numpy())
+        for x, y in zip(hist, hist_r):
+            assert torch.equal(x, y)
+    st.close()
