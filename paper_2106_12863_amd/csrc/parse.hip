@@ -15,9 +15,11 @@
 //   k_line_starts  every newline's position + 1 written at its line number;
 //   k_parse        a workgroup takes 256 consecutive lines, stages their bytes
 //                  in LDS with coalesced loads (as many whole lines at a time
-//                  as fit in 64 KB) and each lane parses its line from LDS
-//                  (a line longer than the staging is read from device
-//                  memory directly).
+//                  as fit in 64 KB), builds a bitmap of the staged commas
+//                  (16 bytes per lane) and each lane finds its line's field
+//                  bounds in the bitmap and parses the fields from LDS (a line
+//                  longer than the staging is read from device memory
+//                  directly).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -167,31 +169,10 @@ __device__ __forceinline__ int32_t days_from_civil(int32_t y, int32_t m, int32_t
     return era * 146097 + doe - 719468;
 }
 
-// Byte access to one line staged in LDS.  comma(c, n) is the first ',' at
-// or after c, or n: it reads whole aligned 32-bit words and finds a comma
-// byte with the zero-byte test on (word ^ 0x2C2C2C2C); bytes of the word
-// before c are set to 0xFF first, so neither they nor a borrow out of them
-// can mark a byte.  Words may reach a few bytes past the line (or the staged
-// bytes: the staging array has 16 bytes of slack); positions at or past n
-// are not taken.
+// Byte access to one line staged in LDS.
 struct LdsLine {
     const uint8_t* p;  // the line's first byte
     __device__ __forceinline__ uint32_t operator[](uint32_t i) const { return p[i]; }
-    __device__ __forceinline__ uint32_t comma(uint32_t c, uint32_t n) const {
-        for (uint32_t i = c; i < n;) {
-            const uint32_t off = (uint32_t)((uintptr_t)(p + i) & 3u);
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(p + i - off);
-            uint32_t x = w ^ 0x2C2C2C2Cu;
-            if (off) x |= 0xFFFFFFFFu >> (32 - 8 * off);
-            const uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;
-            if (z) {
-                const uint32_t at = i - off + (__builtin_ctz(z) >> 3);
-                return at < n ? at : n;
-            }
-            i += 4 - off;
-        }
-        return n;
-    }
 };
 
 // Byte access to one line in device memory (lines too long for the staging):
@@ -299,40 +280,78 @@ __device__ __forceinline__ bool parse_line(const Bytes& b, uint32_t n, int64_t o
     return false;
 }
 
-// parse_line for a line staged in LDS: one pass over the line's aligned
-// 32-bit words finds the commas that bound fields 1, 5, 8 and 21 (an exact
-// per-byte zero test on word ^ 0x2C2C2C2C marks every comma of a word; bytes
-// outside the line are set to 0xFF first), so every lane runs the same loop
-// over words instead of one search per field.  Same rules as parse_line.
-__device__ __forceinline__ bool parse_line_lds(const uint8_t* p, uint32_t n, int64_t origin,
-                                               uint32_t& ts, uint32_t& src, uint32_t& dst,
-                                               uint64_t& nbytes) {
-    const uint32_t off = (uint32_t)((uintptr_t)p & 3u);
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(p - off);
-    // positions of commas 1, 4, 5, 7, 8, 20 and 21 (field f is [comma f-1 + 1, comma f))
-    uint32_t c1 = 0, c4 = 0, c5 = 0, c7 = 0, c8 = 0, c20 = 0, c21 = n;
-    uint32_t k = 0;  // commas seen
-    for (uint32_t j = 0; 4 * j < n + off && k < 21; ++j) {
-        uint32_t x = w[j] ^ 0x2C2C2C2Cu;
-        if (j == 0 && off) x |= 0xFFFFFFFFu >> (32 - 8 * off);  // bytes before the line
-        const uint32_t hi = n + off - 4 * j;                      // bytes at or past n
-        if (hi < 4) x |= 0xFFFFFFFFu << (8 * hi);
-        uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 per comma
-        while (z && k < 21) {
-            const uint32_t at = 4 * j + ((uint32_t)__builtin_ctz(z) >> 3) - off;
-            ++k;
-            if (k == 1) c1 = at;
-            if (k == 4) c4 = at;
-            if (k == 5) c5 = at;
-            if (k == 7) c7 = at;
-            if (k == 8) c8 = at;
-            if (k == 20) c20 = at;
-            if (k == 21) c21 = at;
-            z &= z - 1;
-        }
+// Bit b of the result: byte b of w is ','.  The zero-byte test is exact per
+// byte: for x = w ^ 0x2C2C2C2C, bit 7 of each byte of
+// ((x & 0x7F7F7F7F) + 0x7F7F7F7F) | x is set exactly when that byte of x is
+// not zero (the sums stay inside their bytes); the four flags are then moved
+// from bits 7, 15, 23, 31 to bits 0..3.
+__device__ __forceinline__ uint32_t comma_bits4(uint32_t w) {
+    const uint32_t x = w ^ 0x2C2C2C2Cu;
+    const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
+    uint32_t z = (~t & 0x80808080u) >> 7;  // bit 8b: byte b is a comma
+    z |= z >> 7;
+    z |= z >> 14;
+    return z & 0xFu;
+}
+
+// Position of the r-th (1-based) set bit of m, r <= popcount(m).
+__device__ __forceinline__ uint32_t nth_bit(uint32_t m, uint32_t r) {
+    uint32_t pos = 0;
+    uint32_t c = (uint32_t)__popc(m & 0xFFFFu);
+    if (r > c) { r -= c; m >>= 16; pos += 16; }
+    c = (uint32_t)__popc(m & 0xFFu);
+    if (r > c) { r -= c; m >>= 8; pos += 8; }
+    c = (uint32_t)__popc(m & 0xFu);
+    if (r > c) { r -= c; m >>= 4; pos += 4; }
+    c = (uint32_t)__popc(m & 0x3u);
+    if (r > c) { r -= c; m >>= 2; pos += 2; }
+    return pos + (r > (m & 1u) ? 1u : 0u);
+}
+
+// parse_line for a line staged in LDS at staging bytes [b0, b1), with the
+// staging's comma bitmap (bit i of word j: staged byte 32 j + i is ',').
+// The line's bitmap words give its comma count and, for commas 1, 4, 7 and
+// 20, the word that holds each and its rank there; commas 5, 8 and 21 are
+// the next set bits after 4, 7 and 20 (comma 21 is the line's end when the
+// line has exactly 20).  Field f is [comma f-1 + 1, comma f).  Same rules as
+// parse_line.
+__device__ __forceinline__ bool parse_line_lds(const uint8_t* stage, const uint32_t* bits, uint32_t b0,
+                                               uint32_t b1, int64_t origin, uint32_t& ts, uint32_t& src,
+                                               uint32_t& dst, uint64_t& nbytes) {
+    if (b1 <= b0) return false;  // an empty line has one field
+    const uint32_t w0 = b0 >> 5, w1 = (b1 - 1) >> 5;
+    const uint32_t lo = 0xFFFFFFFFu << (b0 & 31u);
+    const uint32_t hi = 0xFFFFFFFFu >> (31u - ((b1 - 1) & 31u));
+    auto word = [&](uint32_t w) {  // the line's commas in bitmap word w
+        uint32_t m = bits[w];
+        if (w == w0) m &= lo;
+        if (w == w1) m &= hi;
+        return m;
+    };
+    uint32_t k = 0;  // commas in the words before w
+    uint32_t wa = 0, ra = 0, wb = 0, rb = 0, wc = 0, rc = 0, wd = 0, rd = 0;
+    for (uint32_t w = w0; w <= w1; ++w) {
+        const uint32_t c = (uint32_t)__popc(word(w));
+        // comma t is in word w when k < t <= k + c
+        if (0u - k < c) { wa = w; ra = 1u - k; }
+        if (3u - k < c) { wb = w; rb = 4u - k; }
+        if (6u - k < c) { wc = w; rc = 7u - k; }
+        if (19u - k < c) { wd = w; rd = 20u - k; }
+        k += c;
     }
     if (k < 20) return false;  // fewer than 21 fields
-    const LdsLine b{p};
+    // stage position of the first comma after bit q of word w, or b1
+    auto after = [&](uint32_t w, uint32_t q) {
+        uint32_t m = word(w) & (0xFFFFFFFEu << q);
+        while (!m && w < w1) m = word(++w);
+        return m ? 32 * w + (uint32_t)__builtin_ctz(m) : b1;
+    };
+    const uint32_t q1 = nth_bit(word(wa), ra), q4 = nth_bit(word(wb), rb);
+    const uint32_t q7 = nth_bit(word(wc), rc), q20 = nth_bit(word(wd), rd);
+    const uint32_t c1 = 32 * wa + q1 - b0, c4 = 32 * wb + q4 - b0, c5 = after(wb, q4) - b0;
+    const uint32_t c7 = 32 * wc + q7 - b0, c8 = after(wc, q7) - b0;
+    const uint32_t c20 = 32 * wd + q20 - b0, c21 = after(wd, q20) - b0;
+    const LdsLine b{stage + b0};
     return capture_time(b, 0u, c1, origin, ts) && ipv4(b, c4 + 1, c5, src) &&
            ipv4(b, c7 + 1, c8, dst) && count_u64(b, c20 + 1, c21, nbytes);
 }
@@ -353,6 +372,7 @@ struct ParseArgs {
 
 __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes + 16];
+    __shared__ uint32_t s_comma[kStageBytes / 32];  // bit i of word j: stage[32 j + i] is ','
     __shared__ uint64_t s_start[kParseBlock], s_end[kParseBlock];  // the group's line bytes
     for (uint64_t l0 = (uint64_t)blockIdx.x * kParseBlock; l0 < a.n_lines;
          l0 += (uint64_t)gridDim.x * kParseBlock) {
@@ -410,8 +430,19 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
             for (uint64_t k = a0 + 16 * full + threadIdx.x; k < g1; k += kParseBlock)
                 stage[k - a0] = a.text[k];
             __syncthreads();
+            // the comma bitmap of the staged bytes, 16 bytes per lane at a time
+            // (bits past g1 are stale and lie outside every staged line)
+            const uint32_t n_chunk = (uint32_t)((g1 - a0 + 15) / 16);
+            for (uint32_t c = threadIdx.x; c < n_chunk; c += kParseBlock) {
+                const uint4 v = reinterpret_cast<const uint4*>(stage)[c];
+                reinterpret_cast<uint16_t*>(s_comma)[c] =
+                    (uint16_t)(comma_bits4(v.x) | comma_bits4(v.y) << 4 | comma_bits4(v.z) << 8 |
+                               comma_bits4(v.w) << 12);
+            }
+            __syncthreads();
             if (l >= next && l < m)
-                ok = parse_line_lds(stage + (s - a0), (uint32_t)(e - s), a.origin, ts, src, dst, nb);
+                ok = parse_line_lds(stage, s_comma, (uint32_t)(s - a0), (uint32_t)(e - a0), a.origin, ts,
+                                    src, dst, nb);
             __syncthreads();  // the staging is free for the next step
             next = m;
         }
