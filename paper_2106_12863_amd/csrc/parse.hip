@@ -249,9 +249,24 @@ __device__ __forceinline__ bool ipv4(const Bytes& b, uint32_t s, uint32_t e, uin
 template <class Bytes>
 __device__ __forceinline__ bool count_u64(const Bytes& b, uint32_t s, uint32_t e, uint64_t& out) {
     if (e <= s || e - s > 20) return false;
-    uint64_t v = 0;
-    for (uint32_t i = s; i < e; ++i) {
+    // 19 digits stay below 10^19 < 2^64 - 1, so only a 20th digit can
+    // overflow; the first 9 stay below 10^9 and are summed in 32 bits
+    const uint32_t last = e - s == 20 ? e - 1 : e;
+    const uint32_t e9 = last - s > 9 ? s + 9 : last;
+    uint32_t i = s, v9 = 0;
+    for (; i < e9; ++i) {
         const uint32_t c = b[i] - '0';
+        if (c > 9u) return false;
+        v9 = v9 * 10 + c;
+    }
+    uint64_t v = v9;
+    for (; i < last; ++i) {
+        const uint32_t c = b[i] - '0';
+        if (c > 9u) return false;
+        v = v * 10 + c;
+    }
+    if (last != e) {
+        const uint32_t c = b[last] - '0';
         if (c > 9u) return false;
         // v * 10 + c > 2^64 - 1 = 18446744073709551615 exactly when v exceeds
         // floor((2^64 - 1) / 10), or equals it and c > 5

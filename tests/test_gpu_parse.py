@@ -101,6 +101,13 @@ def test_parse_ragged_misaligned_and_long_lines(sinet, torch):
     long_lines = b"".join(r + b"," + (b"y" * (100 + 7 * (i % 90))) + b"\n" for i, r in enumerate(rows))
     cols, exp, bad = _check(sinet, torch, np.frombuffer(long_lines, np.uint8), stext.ORIGIN_DAYS)
     assert bad == 0 and cols["ts"].shape[0] == 600
+    # single lines longer than the whole staging (parsed from device memory):
+    # good ones with a long 24th field, a bad one with a long 21st field, between
+    # ordinary lines and as the last line without newline
+    giant = [rows[1] + b"," + b"z" * 70_001, b",".join(rows[2].split(b",")[:20]) + b"," + b"7" * 66_000]
+    mixed = b"\n".join(rows[:300] + giant[:1] + rows[300:500] + giant[1:] + rows[500:] + giant[:1])
+    cols, exp, bad = _check(sinet, torch, np.frombuffer(mixed, np.uint8), stext.ORIGIN_DAYS, 1)
+    assert cols["ts"].shape[0] == 603 and bad == 1
 
 
 def test_parse_random_bytes_and_capacity(sinet, torch):
