@@ -96,8 +96,20 @@ __global__ void __launch_bounds__(1024) k_scan_counts(uint64_t* __restrict__ cou
 }
 
 // starts[k + 1] = position after the k-th newline (starts[0] = 0).  Each step
-// of a block reads 16 bytes per lane; a lane's newlines are numbered after
-// the ones of the lanes before it (wave scan, then the waves in order).
+// of a block reads 64 contiguous bytes per lane (four 16-byte loads); a
+// lane's newlines are numbered after the ones of the lanes before it (wave
+// scan, then the waves in order).
+__device__ __forceinline__ uint64_t nl_bits16(uint4 v) {  // bit i: byte i of v is '\n'
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint64_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            m |= (uint64_t)(((w[k] >> (8 * q)) & 0xFFu) == 10u ? 1u : 0u) << (4 * k + q);
+    return m;
+}
+
 __global__ void __launch_bounds__(kParseBlock) k_line_starts(const uint8_t* __restrict__ text,
                                                              uint64_t len,
                                                              const uint64_t* __restrict__ first,
@@ -113,22 +125,18 @@ __global__ void __launch_bounds__(kParseBlock) k_line_starts(const uint8_t* __re
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    for (uint64_t st = b0; st < b1; st += 16 * kParseBlock) {
-        const uint64_t p = st + 16 * (uint64_t)threadIdx.x;
-        uint32_t mask = 0;  // bit q: byte p + q is a newline
-        if (vec && p + 16 <= b1) {
-            const uint4 v = *reinterpret_cast<const uint4*>(text + p);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    mask |= (((w[k] >> (8 * q)) & 0xFFu) == 10u ? 1u : 0u) << (4 * k + q);
+    for (uint64_t st = b0; st < b1; st += 64 * kParseBlock) {
+        const uint64_t p = st + 64 * (uint64_t)threadIdx.x;
+        uint64_t mask = 0;  // bit q: byte p + q is a newline
+        if (vec && p + 64 <= b1) {
+            const uint4* v = reinterpret_cast<const uint4*>(text + p);
+            const uint4 v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+            mask = nl_bits16(v0) | nl_bits16(v1) << 16 | nl_bits16(v2) << 32 | nl_bits16(v3) << 48;
         } else {
-            for (int q = 0; q < 16; ++q)
-                if (p + q < b1 && text[p + q] == 10) mask |= 1u << q;
+            for (int q = 0; q < 64; ++q)
+                if (p + q < b1 && text[p + q] == 10) mask |= 1ull << q;
         }
-        const uint32_t c = (uint32_t)__popc(mask);
+        const uint32_t c = (uint32_t)__popcll(mask);
         uint32_t incl = c;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -145,7 +153,7 @@ __global__ void __launch_bounds__(kParseBlock) k_line_starts(const uint8_t* __re
         }
         uint64_t k = before + (incl - c);  // newlines before this lane's first
         while (mask) {
-            const uint32_t q = (uint32_t)__builtin_ctz(mask);
+            const uint32_t q = (uint32_t)__builtin_ctzll(mask);
             starts[k + 1] = p + q + 1;
             ++k;
             mask &= mask - 1;
@@ -295,18 +303,29 @@ __device__ __forceinline__ bool parse_line(const Bytes& b, uint32_t n, int64_t o
     return false;
 }
 
-// Bit b of the result: byte b of w is ','.  The zero-byte test is exact per
-// byte: for x = w ^ 0x2C2C2C2C, bit 7 of each byte of
+// Bit i of the result: byte i of the 16 bytes v is ','.  The zero-byte test
+// is exact per byte: for x = word ^ 0x2C2C2C2C, bit 7 of each byte of
 // ((x & 0x7F7F7F7F) + 0x7F7F7F7F) | x is set exactly when that byte of x is
-// not zero (the sums stay inside their bytes); the four flags are then moved
-// from bits 7, 15, 23, 31 to bits 0..3.
-__device__ __forceinline__ uint32_t comma_bits4(uint32_t w) {
-    const uint32_t x = w ^ 0x2C2C2C2Cu;
-    const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    uint32_t z = (~t & 0x80808080u) >> 7;  // bit 8b: byte b is a comma
-    z |= z >> 7;
-    z |= z >> 14;
-    return z & 0xFu;
+// not zero (the sums stay inside their bytes).  The four words' flags are
+// gathered first (bit 8 b + q: byte b of word q), then packed to 16 bits
+// (bit 4 b + q) and the 4 x 4 bit matrix is transposed (bit 4 q + b).
+__device__ __forceinline__ uint32_t comma_bits16(uint4 v) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t x = w[q] ^ 0x2C2C2C2Cu;
+        const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;  // bit 7 of a byte: not a comma
+        s |= (t >> (7 - q)) & (0x01010101u << q);
+    }
+    s ^= 0x0F0F0F0Fu;
+    uint32_t y = (s | (s >> 4)) & 0x00FF00FFu;
+    y = (y | (y >> 8)) & 0xFFFFu;
+    uint32_t t = (y ^ (y >> 3)) & 0x0A0Au;
+    y ^= t ^ (t << 3);
+    t = (y ^ (y >> 6)) & 0x00CCu;
+    y ^= t ^ (t << 6);
+    return y;
 }
 
 // Position of the r-th (1-based) set bit of m, r <= popcount(m).
@@ -449,10 +468,8 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
             // (bits past g1 are stale and lie outside every staged line)
             const uint32_t n_chunk = (uint32_t)((g1 - a0 + 15) / 16);
             for (uint32_t c = threadIdx.x; c < n_chunk; c += kParseBlock) {
-                const uint4 v = reinterpret_cast<const uint4*>(stage)[c];
                 reinterpret_cast<uint16_t*>(s_comma)[c] =
-                    (uint16_t)(comma_bits4(v.x) | comma_bits4(v.y) << 4 | comma_bits4(v.z) << 8 |
-                               comma_bits4(v.w) << 12);
+                    (uint16_t)comma_bits16(reinterpret_cast<const uint4*>(stage)[c]);
             }
             __syncthreads();
             if (l >= next && l < m)
