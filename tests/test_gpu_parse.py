@@ -76,6 +76,28 @@ def test_parse_generated_day_sample(sinet, torch):
     assert torch.equal(lab1, lab2) and all(torch.equal(x, y) for x, y in zip(h1, h2))
 
 
+def test_parse_full_4gb_chunk(sinet, torch):
+    """The benchmark's chunk and launch: 500,000 lines generated from the
+    middle of the full synthetic day, repeated 40 times on the device
+    (3.97 GB, 20 M lines); every output equals the oracle's parse of the
+    500,000 lines."""
+    wl = sinetgen.config(5)
+    i0, unit, reps = wl.n // 2, 500_000, 40
+    _say("parse 4 GB chunk")
+    buf, _ = stext.session_lines(wl, start=i0, stop=i0 + unit)
+    exp, ebad = oracle.parse(buf, stext.ORIGIN_DAYS)
+    assert ebad == 0
+    dev = torch.from_numpy(buf).cuda().repeat(reps)
+    cols, bad = sinet.parse_sessions(dev, stext.ORIGIN_DAYS, capacity=unit * reps)
+    torch.cuda.synchronize()
+    assert bad == 0 and cols["ts"].shape[0] == unit * reps
+    for k in ("ts", "src", "dst"):
+        got = sinet.to_host_u32(cols[k]).reshape(reps, unit)
+        assert (got == exp[k][None, :]).all(), k
+    got = sinet.to_host_u64(cols["bytes"]).reshape(reps, unit)
+    assert (got == exp["bytes"][None, :]).all()
+
+
 def test_parse_hand_examples(sinet, torch):
     by_origin = {}
     with open(GOLDEN) as f:
