@@ -128,3 +128,33 @@ def test_streamed_with_separate_lookup_pass(sinet, torch, kind):
         for x, y in zip(hist, hist_r):
             assert torch.equal(x, y)
     st.close()
+
+
+def test_streamed_full_day_equals_resident(sinet, torch):
+    """The out-of-core benchmark's day and launch: the full synthetic day
+    (1.6e9 sessions) generated in HBM, held in pinned host memory and streamed
+    in 64 Mi-session chunks with labels into pinned memory; labels and
+    histogram equal one resident pipeline call over the same day."""
+    from sinetgen import gpu as gg
+    wl = sinetgen.config(5)
+    w = wl.window
+    _say("streamed full day", wl.n)
+    dcols = gg.alloc_and_fill(wl)
+    tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch")
+    lab_r, hist_r = sinet.pipeline(tab, dcols["ts"], dcols["src"], dcols["dst"], dcols["bytes"],
+                                   w.t0, w.width, w.n_bins)
+    pin = {}
+    for c, t in dcols.items():
+        pin[c] = torch.empty(wl.n, dtype=t.dtype, pin_memory=True)
+        pin[c].copy_(t)
+    torch.cuda.synchronize()
+    del dcols
+    lab = torch.empty(wl.n, dtype=torch.uint8, pin_memory=True)
+    st = sinet.Streamer(chunk=64 << 20)
+    _, hist = st.pipeline(tab, pin["ts"], pin["src"], pin["dst"], pin["bytes"], w.t0, w.width,
+                          w.n_bins, label=lab)
+    torch.cuda.synchronize()
+    st.close()
+    assert torch.equal(lab.to("cuda"), lab_r)
+    for x, y in zip(hist, hist_r):
+        assert torch.equal(x, y)
