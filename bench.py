@@ -56,6 +56,8 @@ COUNTER_TRAFFIC = {
                  "bytes": 12.98e9},
     "k_watch": {"workload": "watch-fullday-1.6e+09-1177hosts-144x10min",
                 "kernels_sha": "7b136c4cdca9f0c5", "bytes": 14.77e9},
+    "k_rebin_tiles": {"workload": "rebin-4x86.4M1ms-to-24x1h", "sources": ("rebin.hip", "sinet_internal.h"),
+                      "kernels_sha": "7410aff777466a06", "bytes": 2.766e9},
     # the four kernels of one parse call together, summed the same way
     "parse_call": {"workload": "parse-4.0GB-20000000lines", "sources": ("parse.hip", "sinet_internal.h"),
                    "kernels_sha": "4660613f40b86c3f", "bytes": 12.69e9},
@@ -432,7 +434,8 @@ def bench_rebin(args, torch, sinet, sinetgen, gg):
         "config": {"workload": "rebin-4x86.4M1ms-to-24x1h", "n_bins": w.n_bins, "factor": factor,
                    "arrays": 2, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("k_rebin_tiles", "rebin-4x86.4M1ms-to-24x1h"),
                      "kernel": "k_rebin_tiles (two launches per step)",
                      "alg_bytes_per_launch": alg / 2, "launch_ms": ms / 2},
         "forms": {"rebin": {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall}},
