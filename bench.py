@@ -335,7 +335,7 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
     ms_p, min_p, _, _ = time_calls(torch, per_stream, args.steps, args.warmup)
     alg_bytes = BYTES_PER_SESSION * n + BYTES_PER_BIN * bins
     achieved = alg_bytes / (ms_b * 1e-3) / 1e9
-    return {
+    line = {
         "metric": METRIC, "value": n / (ms_b * 1e-3), "unit": "sessions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32,u64",
@@ -351,6 +351,22 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
                   "per_stream_calls": {"ms_per_step": ms_p, "ms_min": min_p,
                                        "sessions_per_s": n / (ms_p * 1e-3)}},
     }
+    if not args.no_cpu:
+        # whole streams in order until about 10 s of oracle time
+        tot_n, tot_s, used = 0, 0.0, 0
+        for wl, c, *_ in built:
+            r = cpu_baseline(wl, c, sinet, wl.n)
+            tot_n += wl.n
+            tot_s += wl.n / r["value"]
+            used += 1
+            if tot_s > 10.0:
+                break
+        line["cpu_baseline"] = {"value": tot_n / tot_s, "unit": "sessions/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the first {used} of the {len(built)} streams, whole "
+                                          f"({tot_n} sessions, {tot_s:.1f} s), each with its own "
+                                          "prefix table, window and bins"}
+    return line
 
 
 def bench_parse(args, torch, sinet, sinetgen, gg):
@@ -425,7 +441,7 @@ def bench_rebin(args, torch, sinet, sinetgen, gg):
     ms, ms_min, wall, _ = time_calls(torch, step, args.steps, args.warmup)
     alg = 2 * 8 * 4 * w.n_bins  # every millisecond bin read once
     achieved = alg / (ms * 1e-3) / 1e9
-    return {
+    line = {
         "metric": "bins/sec summed into one-hour frames on 1 GPU, % HBM roofline",
         "value": 2 * 4 * w.n_bins / (ms * 1e-3), "unit": "bins/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
@@ -440,6 +456,18 @@ def bench_rebin(args, torch, sinet, sinetgen, gg):
                      "alg_bytes_per_launch": alg / 2, "launch_ms": ms / 2},
         "forms": {"rebin": {"ms_per_step": ms, "ms_min": ms_min, "wall_ms": wall}},
     }
+    if not args.no_cpu:
+        import oracle
+        hc, hb = sinet.to_host_u64(c), sinet.to_host_u64(b)  # the whole workload, copies excluded
+        tc = time.perf_counter()
+        oracle.rebin(hc, factor)
+        oracle.rebin(hb, factor)
+        sec = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": 2 * hc.size / sec, "unit": "bins/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the whole step: both arrays, {2 * hc.size} bins "
+                                          f"({sec:.2f} s)"}
+    return line
 
 
 def bench_host(args, torch, sinet, sinetgen, gg):
@@ -489,7 +517,20 @@ def bench_host(args, torch, sinet, sinetgen, gg):
     moved = 20 * wl.n  # columns in (the labels go the other way on the full-duplex link)
     achieved = moved / (ms_pin * 1e-3) / 1e9
     st.close()
-    return {
+    base = None
+    if not args.no_cpu:
+        import oracle
+        n = min(36_000_000, wl.n)
+        i0 = (wl.n - n) // 2
+        hs = {k: v[i0:i0 + n].view(np.uint64 if k == "bytes" else np.uint32) for k, v in page.items()}
+        tc = time.perf_counter()
+        oracle.pipeline(wl.pbase, wl.plen, hs["ts"], hs["src"], hs["dst"], hs["bytes"], w.t0,
+                        w.width, w.n_bins, mode="hash")
+        dt = time.perf_counter() - tc
+        base = {"value": n / dt, "unit": "sessions/s", "cores": 1, "kind": "oracle",
+                "sample": f"sessions [{i0}, {i0 + n}) of the same host-resident day ({n} sessions, "
+                          f"{dt:.1f} s)"}
+    line = {
         "metric": "sessions/sec classify+histogram on 1 GPU from host memory (host link included)",
         "value": wl.n / (ms_pin * 1e-3), "unit": "sessions/s", "n_gpus": 1, "steps": steps,
         "warmup": 1, "ms_per_step": ms_pin, "higher_is_better": True, "scaling": "weak",
@@ -505,6 +546,9 @@ def bench_host(args, torch, sinet, sinetgen, gg):
                   "pageable": {"ms_per_step": ms_page,
                                "sessions_per_s": wl.n / (ms_page * 1e-3)}},
     }
+    if base is not None:
+        line["cpu_baseline"] = base
+    return line
 
 
 def bench_watch(args, torch, sinet, sinetgen, gg):
