@@ -58,6 +58,10 @@ COUNTER_TRAFFIC = {
                 "kernels_sha": "7b136c4cdca9f0c5", "bytes": 14.77e9},
     "k_rebin_tiles": {"workload": "rebin-4x86.4M1ms-to-24x1h", "sources": ("rebin.hip", "sinet_internal.h"),
                       "kernels_sha": "7410aff777466a06", "bytes": 2.766e9},
+    # the eight kernels of one batch graph launch together (the last launch of the run)
+    "batch_graph": {"workload": "batch-64streams-299999969sessions",
+                    "sources": ('batch.hip', 'kernels.hip', 'sinet_internal.h', 'sinet_device.h', 'inout_index.h'),
+                    "kernels_sha": "f6f0fd88b67b2d05", "bytes": 28.15e9},
     # the four kernels of one parse call together, summed the same way
     "parse_call": {"workload": "parse-4.0GB-20000000lines", "sources": ("parse.hip", "sinet_internal.h"),
                    "kernels_sha": "4660613f40b86c3f", "bytes": 12.69e9},
@@ -343,7 +347,9 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
         "config": {"workload": f"batch-{len(streams_wl)}streams-{n}sessions", "n_sessions": n,
                    "n_bins_total": bins, "form": "batched", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("batch_graph",
+                                                 f"batch-{len(streams_wl)}streams-{n}sessions"),
                      "kernel": "one batch graph launch", "alg_bytes_per_launch": alg_bytes,
                      "launch_ms": ms_b},
         "forms": {"batched": {"ms_per_step": ms_b, "ms_min": min_b,
