@@ -181,6 +181,12 @@ __device__ __forceinline__ int32_t days_from_civil(int32_t y, int32_t m, int32_t
 struct LdsLine {
     const uint8_t* p;  // the line's first byte
     __device__ __forceinline__ uint32_t operator[](uint32_t i) const { return p[i]; }
+    // byte i, or 0xFF at or past e; reads up to 3 bytes past a field's end
+    // stay inside the staging (it has 16 bytes of slack), so no branch
+    __device__ __forceinline__ uint32_t upto(uint32_t i, uint32_t e) const {
+        const uint32_t c = p[i];
+        return i < e ? c : 0xFFu;
+    }
 };
 
 // Byte access to one line in device memory (lines too long for the staging):
@@ -188,6 +194,7 @@ struct LdsLine {
 struct GlobalLine {
     const uint8_t* p;
     __device__ __forceinline__ uint32_t operator[](uint32_t i) const { return p[i]; }
+    __device__ __forceinline__ uint32_t upto(uint32_t i, uint32_t e) const { return i < e ? p[i] : 0xFFu; }
     __device__ __forceinline__ uint32_t comma(uint32_t c, uint32_t n) const {
         while (c < n && p[c] != ',') ++c;
         return c;
@@ -230,22 +237,25 @@ __device__ __forceinline__ bool capture_time(const Bytes& b, uint32_t s, uint32_
 
 template <class Bytes>
 __device__ __forceinline__ bool ipv4(const Bytes& b, uint32_t s, uint32_t e, uint32_t& a) {
-    uint32_t v = 0;
-    uint32_t i = s;
+    if (e - s < 7u || e - s > 15u) return false;  // "1.2.3.4" to "255.255.255.255"
+    constexpr uint32_t kDot = (uint32_t)('.' - '0');
+    uint32_t v = 0, i = s;
+#pragma unroll
     for (int part = 0; part < 4; ++part) {
-        uint32_t o = 0;
-        int nd = 0;
-        while (i < e && nd < 4) {
-            const uint32_t c = b[i] - '0';
-            if (c > 9u) break;
-            o = o * 10 + c;
-            ++nd;
-            ++i;
-        }
-        if (nd < 1 || nd > 3 || o > 255) return false;
+        // the octet is the digits at i (a fourth one makes it bad); the byte
+        // after them must be '.' for parts 0-2 and the field's end for part 3
+        const uint32_t d0 = b.upto(i, e) - '0', d1 = b.upto(i + 1, e) - '0';
+        const uint32_t d2 = b.upto(i + 2, e) - '0', d3 = b.upto(i + 3, e) - '0';
+        if (d0 > 9u) return false;
+        const uint32_t nd = d1 > 9u ? 1u : d2 > 9u ? 2u : d3 > 9u ? 3u : 4u;
+        if (nd > 3u) return false;
+        const uint32_t o = nd == 1u ? d0 : nd == 2u ? d0 * 10 + d1 : d0 * 100 + d1 * 10 + d2;
+        if (o > 255u) return false;
+        const uint32_t next = nd == 1u ? d1 : nd == 2u ? d2 : d3;
         v = (v << 8) | o;
+        i += nd;
         if (part < 3) {
-            if (i >= e || b[i] != '.') return false;
+            if (next != kDot) return false;
             ++i;
         }
     }
@@ -258,20 +268,18 @@ template <class Bytes>
 __device__ __forceinline__ bool count_u64(const Bytes& b, uint32_t s, uint32_t e, uint64_t& out) {
     if (e <= s || e - s > 20) return false;
     // 19 digits stay below 10^19 < 2^64 - 1, so only a 20th digit can
-    // overflow; the first 9 stay below 10^9 and are summed in 32 bits
+    // overflow; the digits before it are taken four at a time
     const uint32_t last = e - s == 20 ? e - 1 : e;
-    const uint32_t e9 = last - s > 9 ? s + 9 : last;
-    uint32_t i = s, v9 = 0;
-    for (; i < e9; ++i) {
-        const uint32_t c = b[i] - '0';
-        if (c > 9u) return false;
-        v9 = v9 * 10 + c;
-    }
-    uint64_t v = v9;
-    for (; i < last; ++i) {
-        const uint32_t c = b[i] - '0';
-        if (c > 9u) return false;
-        v = v * 10 + c;
+    uint64_t v = 0;
+    for (uint32_t i = s; i < last; i += 4) {
+        const uint32_t k = last - i < 4u ? last - i : 4u;  // digits in this group
+        const uint32_t d0 = b.upto(i, last) - '0', d1 = b.upto(i + 1, last) - '0';
+        const uint32_t d2 = b.upto(i + 2, last) - '0', d3 = b.upto(i + 3, last) - '0';
+        if (d0 > 9u || (k > 1u && d1 > 9u) || (k > 2u && d2 > 9u) || (k > 3u && d3 > 9u)) return false;
+        const uint32_t g2 = d0 * 10 + d1, g3 = g2 * 10 + d2;
+        const uint32_t g = k == 1u ? d0 : k == 2u ? g2 : k == 3u ? g3 : g3 * 10 + d3;
+        const uint32_t p10 = k == 1u ? 10u : k == 2u ? 100u : k == 3u ? 1000u : 10000u;
+        v = v * p10 + g;
     }
     if (last != e) {
         const uint32_t c = b[last] - '0';
