@@ -70,26 +70,34 @@ __global__ void __launch_bounds__(kParseBlock) k_count_lines(const uint8_t* __re
     if (threadIdx.x == 0) counts[blockIdx.x] = s_sum;
 }
 
-// Exclusive sums of n counts in place, total in counts[n] (one workgroup).
+// Exclusive sums of n counts in place, total in counts[n] (one workgroup):
+// each 1024-count step scans within waves (shuffles), then adds the totals
+// of the waves before and of the steps before.
 __global__ void __launch_bounds__(1024) k_scan_counts(uint64_t* __restrict__ counts, uint32_t n) {
-    __shared__ uint64_t s_part[1024];
+    __shared__ uint64_t s_wave[16];
     __shared__ uint64_t s_carry;
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     for (uint32_t base = 0; base < n; base += 1024) {
         const uint32_t i = base + threadIdx.x;
         const uint64_t x = i < n ? counts[i] : 0ull;
-        s_part[threadIdx.x] = x;
-        __syncthreads();
-        for (uint32_t d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
-            const uint64_t y = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0ull;
-            __syncthreads();
-            s_part[threadIdx.x] += y;
-            __syncthreads();
+        uint64_t incl = x;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(incl, d);
+            if (lane >= (uint32_t)d) incl += y;
         }
-        if (i < n) counts[i] = s_carry + s_part[threadIdx.x] - x;
+        if (lane == 63) s_wave[wave] = incl;
         __syncthreads();
-        if (threadIdx.x == 1023) s_carry += s_part[1023];
+        uint64_t before = s_carry, total = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < wave) before += s_wave[w];
+            total += s_wave[w];
+        }
+        if (i < n) counts[i] = before + incl - x;
+        __syncthreads();  // every lane has read s_wave and s_carry
+        if (threadIdx.x == 0) s_carry += total;
         __syncthreads();
     }
     if (threadIdx.x == 0) counts[n] = s_carry;
