@@ -424,17 +424,27 @@ __global__ void __launch_bounds__(kParseBlock) k_parse(ParseArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[kStageBytes + 16];
     __shared__ uint32_t s_comma[kStageBytes / 32];  // bit i of word j: stage[32 j + i] is ','
     __shared__ uint64_t s_start[kParseBlock], s_end[kParseBlock];  // the group's line bytes
-    for (uint64_t l0 = (uint64_t)blockIdx.x * kParseBlock; l0 < a.n_lines;
-         l0 += (uint64_t)gridDim.x * kParseBlock) {
+    // start and end of the bytes of this lane's line in the group at l0x
+    // (0, 0 past the last line); the next group's are loaded while this
+    // group is parsed
+    auto bounds = [&](uint64_t l0x, uint64_t& xs, uint64_t& xg) {
+        const uint64_t lx = l0x + threadIdx.x;
+        xs = xg = 0;
+        if (lx < a.n_lines) {
+            xs = a.starts[lx];
+            xg = lx < a.n_nl ? a.starts[lx + 1] : a.len;
+        }
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * kParseBlock;
+    uint64_t ns = 0, ng = 0;
+    bounds((uint64_t)blockIdx.x * kParseBlock, ns, ng);
+    for (uint64_t l0 = (uint64_t)blockIdx.x * kParseBlock; l0 < a.n_lines; l0 += stride) {
         const uint64_t l1 = l0 + kParseBlock < a.n_lines ? l0 + kParseBlock : a.n_lines;
         const uint64_t l = l0 + threadIdx.x;
         // this lane's line [s, e) (without its newline) and the end of its bytes
-        uint64_t s = 0, e = 0, g = 0;
-        if (l < l1) {
-            s = a.starts[l];
-            g = l < a.n_nl ? a.starts[l + 1] : a.len;
-            e = l < a.n_nl ? g - 1 : a.len;
-        }
+        const uint64_t s = ns, g = ng;
+        const uint64_t e = l < l1 ? (l < a.n_nl ? g - 1 : a.len) : 0;
+        if (l0 + stride < a.n_lines) bounds(l0 + stride, ns, ng);
         s_start[threadIdx.x] = s;
         s_end[threadIdx.x] = g;  // read after the first barrier below
         uint32_t ts = kBadTs, src = 0, dst = 0;
