@@ -151,3 +151,52 @@ def mlp_grad_abs_sum(params, x, y):
     a = 2.0 * np.abs(r) / n
     dz = (a[:, None] * np.abs(w2)[None, :]) * (z > 0.0)
     return np.concatenate([dz.T @ np.abs(x), dz.sum(axis=0), h.T @ a, [a.sum()]])
+
+
+# ---------------------------------------------------------------------------
+# Rounded positions in float32.  A model's prediction becomes an integer
+# position (the start of the bounded search), so the measured bound depends on
+# the precision the prediction is taken in; these functions take it in the
+# float32 arithmetic of the lookups, one IEEE rounding per operation and no
+# fused multiply-add, then clamp to [0, m - 1] and round to the nearest
+# integer (ties to even).
+# ---------------------------------------------------------------------------
+def _clamp_round(p, m):
+    p = np.fmin(np.fmax(p, np.float32(0.0)), np.float32(m - 1))   # NaN -> 0
+    return np.rint(p).astype(np.int64)
+
+
+def pla_position_f32(knot, c, g, a, m):
+    """Rounded PLA position of addresses a: the last knot <= a picks the
+    segment s, then p = c_s + g_s * float32(a - knot_s)."""
+    knot = np.asarray(knot, dtype=np.uint32)
+    a = np.asarray(a, dtype=np.uint32)
+    s = np.searchsorted(knot, a, side="right") - 1
+    d = (a - knot[s]).astype(np.float32)                 # a - knot_s < 2^32, rounded once
+    p = np.asarray(c, np.float32)[s] + np.asarray(g, np.float32)[s] * d
+    return _clamp_round(p.astype(np.float32), m)
+
+
+def mlp_position_f32(params, a, m):
+    """Rounded MLP position: x = float32(a) * 2^-32, f = b2 + sum_k w2_k
+    relu(w1_k x + b1_k) accumulated in k order, p = f * float32(m)."""
+    w = np.asarray(params, dtype=np.float32)
+    x = np.asarray(a, dtype=np.uint32).astype(np.float32) * np.float32(2.0 ** -32)
+    f = np.full(x.shape, w[48], dtype=np.float32)
+    for k in range(H):
+        z = w[k] * x + w[H + k]
+        f = f + w[2 * H + k] * np.maximum(z, np.float32(0.0))
+    return _clamp_round(f * np.float32(m), m)
+
+
+def max_error_rounded(pos_fn, B: np.ndarray) -> int:
+    """max over intervals j of |pos_fn(a) - j| at a = B[j] and a = B[j+1] - 1
+    (the last interval ends at 2^32 - 1): the bound a lookup's search window
+    must cover, for a prediction monotone inside every interval."""
+    m = B.shape[0]
+    j = np.arange(m, dtype=np.int64)
+    lo = B.astype(np.uint32)
+    hi = np.empty(m, np.uint32)
+    hi[:-1] = B[1:] - 1
+    hi[-1] = 0xFFFFFFFF
+    return int(max(np.max(np.abs(pos_fn(lo) - j)), np.max(np.abs(pos_fn(hi) - j))))
