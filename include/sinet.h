@@ -389,17 +389,24 @@ sinet_status sinet_streamer_destroy(sinet_streamer* s);
  * the calls made since timing was last enabled.  Each phase is bracketed by
  * a pair of HIP events recorded on the call's own stream (none while the
  * stream is being captured into a graph), so a phase's figure is the device
- * time of its kernels on that stream. */
+ * time of its kernels on that stream.  Phases of the two reduces:
+ *                 records reduce                 sliding-window reduce
+ *   lookup_ms     lookup pass storing labels     lookup pass storing labels
+ *                 (global-memory searches only)  (every lookup kind)
+ *   stage1_ms     k_stage1: classify, bin,       k_window: bin, window in LDS,
+ *                 partition into records         one write of every bin
+ *   index_ms      segment scan, directory fill   k_window_bounds: pieces' bins
+ *   stage2_ms     k_stage2: block reduction      k_window_fixup: boundary spills
+ *   far_ms        far pass (global atomics)      k_window_far (global atomics)
+ * For n_bins <= 2048 stage1_ms is the single private-histogram pass. */
 typedef struct {
-    double lookup_ms;   /* separate lookup pass that stores labels before stage 1
-                           (trie, learned and sampled-boundary searches); 0 when fused */
-    double stage1_ms;   /* k_stage1: classify, bin, partition into records; for
-                           n_bins <= 2048 the single private-histogram pass instead */
-    double index_ms;    /* per-block segment scan and directory fill */
-    double stage2_ms;   /* k_stage2: block reduction, one write of every bin */
-    double far_ms;      /* far pass (out-of-partition sessions, global atomics) */
+    double lookup_ms;
+    double stage1_ms;
+    double index_ms;
+    double stage2_ms;
+    double far_ms;
     uint64_t calls;     /* timed sinet_histogram / sinet_pipeline calls */
-    uint64_t stage1_launches;  /* stage-1 (or private-pass) launches among them */
+    uint64_t stage1_launches;  /* stage-1 (or private-pass, or window) launches among them */
 } sinet_timing;
 
 /* on != 0: start timing every later sinet_histogram / sinet_pipeline call of
@@ -411,6 +418,30 @@ sinet_status sinet_timing_enable(int on);
 /* Wait for the recorded events and return the sums since the last enable.
  * Errors: INVALID_ARG (out NULL), HIP (event failure). */
 sinet_status sinet_timing_read(sinet_timing* out);
+
+/* Reduce used by sinet_histogram / sinet_pipeline (and the streamer) when
+ * the histogram has more than 2048 bins (smaller ones are always reduced in
+ * LDS per workgroup).  Both reduces give bit-identical results for any
+ * input; they differ in speed and workspace:
+ *   RECORDS  the two-stage map-reduce of the sections "Two-stage Map-Reduce
+ *            with tiling pattern" and "Reduce": stage 1 writes one 4-byte
+ *            record per session grouped by 1024-bin block, stage 2 reduces
+ *            each block in LDS and writes its bins (about 6 bytes of
+ *            workspace per session);
+ *   WINDOW   the same Map and Reduce in one pass over labelled sessions: a
+ *            workgroup walks a contiguous range of nearly time-sorted
+ *            sessions with the bins it touches in LDS and writes every bin
+ *            once (labels are stored by a lookup pass first; about 1 byte
+ *            of workspace per session plus 330 MB);
+ *   AUTO     WINDOW from 2^22 sessions on, else RECORDS (the default).
+ * Process-wide; takes effect for calls made after it returns.
+ * Errors: INVALID_ARG (unknown mode). */
+typedef enum {
+    SINET_REDUCE_AUTO = 0,
+    SINET_REDUCE_RECORDS = 1,
+    SINET_REDUCE_WINDOW = 2
+} sinet_reduce;
+sinet_status sinet_set_reduce(sinet_reduce mode);
 
 #ifdef __cplusplus
 }

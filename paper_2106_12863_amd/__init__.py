@@ -116,6 +116,7 @@ _sig("sinet_batch_run", [P, P])
 _sig("sinet_batch_plan_destroy", [P])
 _sig("sinet_timing_enable", [I32])
 _sig("sinet_timing_read", [ctypes.POINTER(Timing)])
+_sig("sinet_set_reduce", [I32])
 
 
 class SinetError(RuntimeError):
@@ -600,6 +601,18 @@ def timing_read() -> dict:
     t = Timing()
     _check(_lib.sinet_timing_read(ctypes.byref(t)), "sinet_timing_read")
     return {name: getattr(t, name) for name, _ in Timing._fields_}
+
+
+REDUCES = {"auto": 0, "records": 1, "window": 2}
+
+
+def set_reduce(mode: str = "auto"):
+    """Reduce of later histogram / pipeline calls: "records" (two-stage
+    partition into 4-byte records), "window" (sliding window of bins in LDS
+    over labelled sessions) or "auto" (window from 2^22 sessions on)."""
+    if mode not in REDUCES:
+        raise ValueError(f"reduce must be one of {sorted(REDUCES)}")
+    _check(_lib.sinet_set_reduce(REDUCES[mode]), "sinet_set_reduce")
 
 
 # host <-> device helpers for uint32/uint64 data held in signed tensors

@@ -678,6 +678,8 @@ sinet_status sinet_mlp_loss_grad(const float* params, const float* x, const floa
 
 sinet_status sinet_timing_enable(int on) { return timing_enable(on); }
 
+sinet_status sinet_set_reduce(sinet_reduce mode) { return set_reduce((int)mode); }
+
 sinet_status sinet_timing_read(sinet_timing* out) {
     if (!out) return fail(SINET_ERR_INVALID_ARG, "out is NULL");
     double ms[PH_COUNT];

@@ -31,12 +31,14 @@
 
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
 #include <vector>
 
 #include "inout_index.h"
+#include "pass_common.h"
 #include "sinet_device.h"
 #include "sinet_internal.h"
 
@@ -325,74 +327,6 @@ __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, con
         }
     }
 }
-
-// Column and table pointers always address device (global) memory.  Where the
-// kernels read them from a descriptor in memory (the batch kernels), the
-// compiler can no longer infer that and falls back to flat accesses, whose
-// waits are tied to LDS operations; these casts restore global accesses.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T* glob(const T* q) {
-    return (const __attribute__((address_space(1))) T*)q;
-}
-template <class T>
-__device__ __forceinline__ __attribute__((address_space(1))) T* glob(T* q) {
-    return (__attribute__((address_space(1))) T*)q;
-}
-typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint4 gload4(const uint32_t* q) {  // q 16-byte aligned
-    const u32x4_t v = *glob(reinterpret_cast<const u32x4_t*>(q));
-    return make_uint4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ ulonglong2 gload2(const uint64_t* q) {
-    const u64x2_t v = *glob(reinterpret_cast<const u64x2_t*>(q));
-    return make_ulonglong2(v.x, v.y);
-}
-__device__ __forceinline__ void gstore4(uint32_t* q, uint4 v) {
-    *glob(reinterpret_cast<u32x4_t*>(q)) = u32x4_t{v.x, v.y, v.z, v.w};
-}
-
-// ---------------------------------------------------------------------------
-// binning
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bin_of(uint32_t x, uint32_t width, uint64_t magic) {
-    // floor(x / width) for 32-bit x: with c = ceil(2^64 / width) the high 64
-    // bits of x * c equal the quotient (Lemire, Kaser, Kurz, "Faster remainder
-    // by direct computation", 2019).  width == 1 skips the multiply.
-    if (width == 1u) return x;
-    uint64_t t = (uint64_t)x * (uint32_t)magic;
-    uint64_t u = (uint64_t)x * (uint32_t)(magic >> 32) + (t >> 32);
-    return (uint32_t)(u >> 32);
-}
-
-// In-window test and bin of one session (the Map step's key).
-__device__ __forceinline__ bool in_window(const PassParams& p, uint32_t ts, uint32_t& bin) {
-    bin = bin_of(ts - p.t0, p.width, p.magic);
-    return ts >= p.t0 && bin < p.n_bins;
-}
-
-struct Dropped {
-    unsigned long long c[4];
-    unsigned long long b[4];
-    __device__ __forceinline__ void add(uint32_t lab, uint64_t nbytes) {
-#pragma unroll
-        for (uint32_t l = 0; l < 4; ++l) {  // constant indices: stays in registers
-            const bool h = lab == l;
-            c[l] += h ? 1ull : 0ull;
-            b[l] += h ? nbytes : 0ull;
-        }
-    }
-    __device__ __forceinline__ void flush(unsigned long long* out) const {
-        if (!out) return;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            if (c[l]) {
-                atomicAdd(out + 2 * l, c[l]);
-                atomicAdd(out + 2 * l + 1, b[l]);
-            }
-        }
-    }
-};
 
 enum HistMode : int {
     H_NONE = 0,     // labels / institutions / positions only
@@ -723,24 +657,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
 // part 0 carries the session's count.  0xFFFFFFFF is the null record (a part 3
 // holds at most bit 51, so no real record has that value).
 // ---------------------------------------------------------------------------
-// Minimum over the 64 lanes of a wave by DPP row shifts and row broadcasts
-// (lanes a row shift or a masked row leaves without a source keep ~0, the
-// identity of min); lane 63 ends with the result.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_min_step(uint32_t x) {
-    return min(x, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)x, CTRL, ROW_MASK, 0xF,
-                                                         false));
-}
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-    x = dpp_min_step<0x111, 0xF>(x);  // row_shr:1
-    x = dpp_min_step<0x112, 0xF>(x);  // row_shr:2
-    x = dpp_min_step<0x114, 0xF>(x);  // row_shr:4
-    x = dpp_min_step<0x118, 0xF>(x);  // row_shr:8
-    x = dpp_min_step<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
-    x = dpp_min_step<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-}
-
 // Raw column words of one lane's four sessions (loaded one chunk ahead).
 struct Raw4 {
     uint4 src, dst, ts;
@@ -2286,12 +2202,28 @@ sinet_status ws_free(void* ptr, hipStream_t s) {
     return check_hip(hipFreeAsync(ptr, s), "workspace free");
 }
 
-// Histogram strategy for a window: small windows are privatised in LDS.
+// Which reduce the histogram calls use (sinet_set_reduce).
+static std::atomic<int> g_reduce{SINET_REDUCE_AUTO};
+
+sinet_status set_reduce(int mode) {
+    if (mode != SINET_REDUCE_AUTO && mode != SINET_REDUCE_RECORDS && mode != SINET_REDUCE_WINDOW)
+        return fail(SINET_ERR_INVALID_ARG, "unknown reduce");
+    g_reduce.store(mode);
+    return SINET_OK;
+}
+
+// Histogram strategy for a window: small windows are privatised in LDS; long
+// inputs take the sliding-window reduce, the rest the partitioned records.
+constexpr uint64_t kWindowMinSessions = 1ull << 22;
+constexpr int H_WINDOW = 4;
+
 int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n) {
     const size_t priv = 12ull * 4 * n_bins;
     const size_t tab = kind == KK_LABEL_IN ? 0 : t.lds_bytes;
     if (n_bins <= 2048 && priv + tab + 64 <= 96 * 1024) return H_PRIVATE;
-    (void)n;
+    const int mode = g_reduce.load();
+    if (mode == SINET_REDUCE_WINDOW) return H_WINDOW;
+    if (mode == SINET_REDUCE_AUTO && n >= kWindowMinSessions) return H_WINDOW;
     return 3;  // partitioned
 }
 
@@ -2316,6 +2248,51 @@ static PassParams advance(const PassParams& p, uint64_t off) {
     q.src_inst = p.src_inst ? p.src_inst + off : nullptr;
     q.dst_inst = p.dst_inst ? p.dst_inst + off : nullptr;
     return q;
+}
+
+// Sliding-window reduce (window.hip): the labels first (a lookup pass that
+// stores them, unless they are given), then the window pass, the fix-up of
+// the bins at the pieces' boundaries and the far path.
+static sinet_status run_window(const PassParams& p, uint32_t kind, int accumulate, hipStream_t s) {
+    const uint32_t P = win_pieces(p.n);
+    const size_t wsb = win_ws_bytes(p.n, P);
+    const bool lookup = kind != KK_LABEL_IN;
+    const size_t lab_bytes = lookup && !p.label_out ? al256(p.n) : 0;
+    void* ws = nullptr;
+    sinet_status st = ws_alloc(&ws, wsb + lab_bytes, s);
+    if (st != SINET_OK) return st;
+    PassParams q = p;
+    if (lookup) {
+        PassParams lq = p;
+        if (!lq.label_out) lq.label_out = (uint8_t*)ws + wsb;
+        lq.pos_out = nullptr;
+        FarList none{};
+        PhaseScope ph(PH_LOOKUP, s);
+        st = launch_k_pass(lq, kind, H_NONE, vector_ok(lq, kind, false), none, 0, s);
+        q.label_in = lq.label_out;
+    }
+    q.label_out = nullptr;
+    q.src_inst = nullptr;
+    q.dst_inst = nullptr;
+    const WinArgs a = win_carve(ws, q, P, accumulate);
+    if (st == SINET_OK) {
+        PhaseScope ph(PH_INDEX, s);
+        st = win_launch_bounds(a, s);
+    }
+    if (st == SINET_OK) {
+        PhaseScope ph(PH_STAGE1, s);
+        st = win_launch_main(a, s);
+    }
+    if (st == SINET_OK) {
+        PhaseScope ph(PH_STAGE2, s);
+        st = win_launch_fixup(a, s);
+    }
+    if (st == SINET_OK) {
+        PhaseScope ph(PH_FAR, s);
+        st = win_launch_far(a, s);
+    }
+    const sinet_status st2 = ws_free(ws, s);
+    return st != SINET_OK ? st : st2;
 }
 
 sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s) {
@@ -2349,6 +2326,7 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
         return launch_k_pass(p, kind, H_PRIVATE, vector_ok(p, kind, true), none,
                              12ull * 4 * p.n_bins + 8, s);
     }
+    if (strat == H_WINDOW) return run_window(p, kind, accumulate, s);
     // partitioned: pieces of at most kMaxPiece sessions (32-bit slot indices)
     int acc = accumulate;
     for (uint64_t lo = 0; lo < p.n; lo += kMaxPiece) {

@@ -129,6 +129,38 @@ struct PassParams {
     uint64_t magic;             // ceil(2^64 / width) for width >= 2
 };
 
+// Sliding-window histogram (window.hip): one workgroup per piece (a
+// contiguous range of sessions), a ring of kWinBins bins x 4 labels in LDS.
+constexpr uint32_t kWinBins = 10192;
+constexpr uint32_t kWinStep = 4096;  // sessions of one window step (4 per lane)
+
+struct WinArgs {
+    const uint32_t* ts;             // session columns (labels given)
+    const uint64_t* bytes;
+    const uint8_t* label;
+    unsigned long long* count;      // [4][n_bins] outputs, dropped [4][2] or NULL
+    unsigned long long* hbytes;
+    unsigned long long* dropped;
+    uint64_t n;
+    uint64_t magic;                 // ceil(2^64 / width) for width >= 2
+    uint32_t t0, width, n_bins;
+    uint32_t pieces;                // P workgroups, one piece of sessions each
+    uint32_t* est;                  // [P] median bin around piece q's first session
+    uint32_t* T;                    // [P + 1] owned bins of piece q: [T[q], T[q+1])
+    uint32_t* V;                    // [P] first bin of piece q's left spill that was written
+    uint32_t* E;                    // [P] end of piece q's right spill that was written
+    uint32_t* counters;             // [4] -, events, event overflow, -
+    uint32_t* far_n;                // [P] steps of piece q holding far sessions
+    uint32_t* far_steps;            // [steps] those steps, piece q's listed from its first
+                                    // step's slot on
+    uint32_t* far_bits;             // [steps * kWinStep / 32] far-session bits of listed steps
+    unsigned long long* events;     // [ev_cap] bin << 3 | label << 1 | wrap
+    unsigned long long* spill;      // [P][left, right][count, bytes][4][kWinBins]
+    uint64_t ev_cap;
+    uint32_t vec;                   // 16-byte column loads allowed
+    int accumulate;
+};
+
 // One stream of a batch as the batch kernels see it.
 struct BatchStreamDev {
     PassParams p;               // label view of its table, columns, outputs, window
@@ -201,6 +233,7 @@ sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStr
 // phase timing of run_hist (event pairs on the launch stream)
 enum TimedPhase { PH_LOOKUP = 0, PH_STAGE1, PH_INDEX, PH_STAGE2, PH_FAR, PH_COUNT };
 sinet_status timing_enable(int on);
+sinet_status set_reduce(int mode);
 sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches);
 size_t part_ws_bytes(uint64_t n, uint32_t n_bins);
 PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins);
@@ -220,6 +253,15 @@ sinet_status ws_alloc(void** ptr, size_t bytes, hipStream_t s);
 sinet_status ws_free(void* ptr, hipStream_t s);
 uint32_t device_cu_count();
 uint64_t div_magic(uint32_t width);
+
+// sliding-window histogram (window.hip)
+uint32_t win_pieces(uint64_t n);
+size_t win_ws_bytes(uint64_t n, uint32_t pieces);
+WinArgs win_carve(void* base, const PassParams& p, uint32_t pieces, int accumulate);
+sinet_status win_launch_bounds(const WinArgs& a, hipStream_t s);
+sinet_status win_launch_main(const WinArgs& a, hipStream_t s);
+sinet_status win_launch_fixup(const WinArgs& a, hipStream_t s);
+sinet_status win_launch_far(const WinArgs& a, hipStream_t s);
 
 // batch kernels (kernels.hip)
 sinet_status launch_batch_stage1(uint32_t kind, const BatchArgs& a, const PartWs& w, size_t lds,
