@@ -385,6 +385,23 @@ sinet_status sinet_streamer_pipeline(sinet_streamer* s, const sinet_table* t,
 
 sinet_status sinet_streamer_destroy(sinet_streamer* s);
 
+/* sinet_pipeline without allocating: for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as
+ * sinet_pipeline, but its workspace (the sliding-window reduce's piece
+ * bounds, spill rows, far bitmap and event list, and the labels when `label`
+ * is NULL) is carved from a static 128 MiB device array of the library,
+ * which every GPU the library runs on holds until the process ends.  It
+ * calls no allocator: no hipMalloc, no pool, no timing events (phase timing
+ * does not see it).  Limits: at most 2^25 sessions per call (larger inputs:
+ * call it on chunks with accumulate = 1); INVALID_ARG beyond that, checked
+ * before anything is enqueued.  Every call on one GPU uses the same array,
+ * so calls that overlap on one GPU (different host threads or streams
+ * running at the same time) race and must be serialised by the caller. */
+sinet_status sinet_pipeline_noalloc(const sinet_table* t, const sinet_columns* cols,
+                                    const sinet_window* win, uint8_t* label, sinet_hist* out,
+                                    int accumulate, hipStream_t stream);
+
 /* Device time of the phases of sinet_histogram / sinet_pipeline, summed over
  * the calls made since timing was last enabled.  Each phase is bracketed by
  * a pair of HIP events recorded on the call's own stream (none while the

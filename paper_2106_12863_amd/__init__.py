@@ -100,6 +100,8 @@ _sig("sinet_discriminate", [P, P, P, U64, P, P, P, P])
 _sig("sinet_histogram", [P, P, P, U64, ctypes.POINTER(Window), ctypes.POINTER(Hist), I32, P])
 _sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                         ctypes.POINTER(Hist), I32, P])
+_sig("sinet_pipeline_noalloc", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
+                                ctypes.POINTER(Hist), I32, P])
 _sig("sinet_watch_histogram", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), U32,
                                ctypes.POINTER(Hist), I32, P])
 _sig("sinet_rebin", [P, U32, U32, U32, P, P])
@@ -363,6 +365,28 @@ def pipeline(table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: in
                                ctypes.byref(h), int(accumulate), _stream(ts.device)),
            "sinet_pipeline")
     return lab, out
+
+
+def pipeline_noalloc(table: Table, ts, src, dst, nbytes, t0: int, width: int, n_bins: int, label,
+                     out, accumulate: bool = False):
+    """sinet_pipeline_noalloc: the pipeline with the library's static device
+    workspace (at most 2^25 sessions per call).  The outputs are the
+    caller's: `label` a uint8 tensor of n or None, `out` (count, bytes,
+    dropped); nothing is allocated here either."""
+    _dev_check(ts, src, dst, nbytes)
+    n = ts.numel()
+    _check_columns(n, ts, src, dst, nbytes)
+    if label is not None:
+        _sized(label, 1, n, "label")
+    _check_hist(out, n_bins)
+    c = Columns(_ptr(ts), _ptr(src), _ptr(dst), _ptr(nbytes), n)
+    w = Window(t0, width, n_bins)
+    h = _hist_struct(out)
+    _check(_lib.sinet_pipeline_noalloc(table.handle, ctypes.byref(c), ctypes.byref(w),
+                                       _ptr(label) if label is not None else None, ctypes.byref(h),
+                                       int(accumulate), _stream(ts.device)),
+           "sinet_pipeline_noalloc")
+    return label, out
 
 
 WATCH_SRC, WATCH_DST = 0, 1

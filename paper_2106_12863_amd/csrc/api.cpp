@@ -209,6 +209,48 @@ static sinet_status clear_hist(const sinet_window* w, sinet_hist* h, hipStream_t
     return st;
 }
 
+// Argument checks and pass parameters of a pipeline call; *done when nothing
+// is left to run (no sessions: the histogram was cleared unless accumulating).
+sinet_status pipeline_prepare(const sinet_table* t, const sinet_columns* cols, const sinet_window* win,
+                              uint8_t* label, sinet_hist* out, int accumulate, hipStream_t stream,
+                              PassParams* pp, bool* done) {
+    *done = false;
+    sinet_status st = check_usable(t);
+    if (st != SINET_OK) return st;
+    st = check_window(win);
+    if (st != SINET_OK) return st;
+    if (!cols) return fail(SINET_ERR_INVALID_ARG, "columns are NULL");
+    if (!out || !out->count || !out->bytes) return fail(SINET_ERR_INVALID_ARG, "histogram output is NULL");
+    if (cols->n && (!cols->ts || !cols->src || !cols->dst || !cols->bytes))
+        return fail(SINET_ERR_INVALID_ARG, "column is NULL");
+    if (!accumulate && (cols->n == 0 || out->dropped)) {
+        st = cols->n == 0 ? clear_hist(win, out, stream)
+                          : launch_zero((unsigned long long*)out->dropped, 8, stream);
+        if (st != SINET_OK) return st;
+    }
+    if (cols->n == 0) {
+        *done = true;
+        return SINET_OK;
+    }
+    PassParams& p = *pp;
+    memset(&p, 0, sizeof(p));
+    p.t = label_view(t, true);
+    p.ts = cols->ts;
+    p.src = cols->src;
+    p.dst = cols->dst;
+    p.bytes = cols->bytes;
+    p.label_out = label;
+    p.count = (unsigned long long*)out->count;
+    p.hbytes = (unsigned long long*)out->bytes;
+    p.dropped = (unsigned long long*)out->dropped;
+    p.n = cols->n;
+    p.t0 = win->t0_ms;
+    p.width = win->width_ms;
+    p.n_bins = win->n_bins;
+    p.magic = div_magic(win->width_ms);
+    return SINET_OK;
+}
+
 }  // namespace sinet
 
 using namespace sinet;
@@ -601,36 +643,10 @@ sinet_status sinet_histogram(const uint32_t* ts, const uint64_t* bytes, const ui
 
 sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols, const sinet_window* win,
                             uint8_t* label, sinet_hist* out, int accumulate, hipStream_t stream) {
-    sinet_status st = check_usable(t);
-    if (st != SINET_OK) return st;
-    st = check_window(win);
-    if (st != SINET_OK) return st;
-    if (!cols) return fail(SINET_ERR_INVALID_ARG, "columns are NULL");
-    if (!out || !out->count || !out->bytes) return fail(SINET_ERR_INVALID_ARG, "histogram output is NULL");
-    if (cols->n && (!cols->ts || !cols->src || !cols->dst || !cols->bytes))
-        return fail(SINET_ERR_INVALID_ARG, "column is NULL");
-    if (!accumulate && (cols->n == 0 || out->dropped)) {
-        st = cols->n == 0 ? clear_hist(win, out, stream)
-                          : launch_zero((unsigned long long*)out->dropped, 8, stream);
-        if (st != SINET_OK) return st;
-    }
-    if (cols->n == 0) return SINET_OK;
     PassParams p;
-    memset(&p, 0, sizeof(p));
-    p.t = label_view(t, true);
-    p.ts = cols->ts;
-    p.src = cols->src;
-    p.dst = cols->dst;
-    p.bytes = cols->bytes;
-    p.label_out = label;
-    p.count = (unsigned long long*)out->count;
-    p.hbytes = (unsigned long long*)out->bytes;
-    p.dropped = (unsigned long long*)out->dropped;
-    p.n = cols->n;
-    p.t0 = win->t0_ms;
-    p.width = win->width_ms;
-    p.n_bins = win->n_bins;
-    p.magic = div_magic(win->width_ms);
+    bool done = false;
+    const sinet_status st = pipeline_prepare(t, cols, win, label, out, accumulate, stream, &p, &done);
+    if (st != SINET_OK || done) return st;
     return run_hist(p, PASS_LABEL | PASS_HIST, accumulate, stream);
 }
 

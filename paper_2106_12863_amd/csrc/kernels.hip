@@ -1954,7 +1954,8 @@ uint64_t g_tm_calls = 0;
 
 class PhaseScope {
    public:
-    PhaseScope(int phase, hipStream_t s) : phase_(phase), s_(s) {
+    PhaseScope(int phase, hipStream_t s, bool enabled = true) : phase_(phase), s_(s) {
+        if (!enabled) return;
         {
             std::lock_guard<std::mutex> g(g_tm_mu);
             if (!g_tm_on) return;
@@ -2202,6 +2203,8 @@ sinet_status ws_free(void* ptr, hipStream_t s) {
     return check_hip(hipFreeAsync(ptr, s), "workspace free");
 }
 
+constexpr int H_WINDOW = 4;
+
 // Which reduce the histogram calls use (sinet_set_reduce).
 static std::atomic<int> g_reduce{SINET_REDUCE_AUTO};
 
@@ -2215,7 +2218,6 @@ sinet_status set_reduce(int mode) {
 // Histogram strategy for a window: small windows are privatised in LDS; long
 // inputs take the sliding-window reduce, the rest the partitioned records.
 constexpr uint64_t kWindowMinSessions = 1ull << 22;
-constexpr int H_WINDOW = 4;
 
 int hist_strategy(const DevTable& t, uint32_t kind, uint32_t n_bins, uint64_t n) {
     const size_t priv = 12ull * 4 * n_bins;
@@ -2253,21 +2255,20 @@ static PassParams advance(const PassParams& p, uint64_t off) {
 // Sliding-window reduce (window.hip): the labels first (a lookup pass that
 // stores them, unless they are given), then the window pass, the fix-up of
 // the bins at the pieces' boundaries and the far path.
-static sinet_status run_window(const PassParams& p, uint32_t kind, int accumulate, hipStream_t s) {
-    const uint32_t P = win_pieces(p.n);
+// With the workspace given: ws holds win_ws_bytes(n, P) bytes, then (when a
+// lookup pass runs and the caller stores no labels) n bytes of labels.
+static sinet_status run_window_in(const PassParams& p, uint32_t kind, int accumulate, hipStream_t s,
+                                  void* ws, uint32_t P, bool timed) {
     const size_t wsb = win_ws_bytes(p.n, P);
     const bool lookup = kind != KK_LABEL_IN;
-    const size_t lab_bytes = lookup && !p.label_out ? al256(p.n) : 0;
-    void* ws = nullptr;
-    sinet_status st = ws_alloc(&ws, wsb + lab_bytes, s);
-    if (st != SINET_OK) return st;
+    sinet_status st = SINET_OK;
     PassParams q = p;
     if (lookup) {
         PassParams lq = p;
         if (!lq.label_out) lq.label_out = (uint8_t*)ws + wsb;
         lq.pos_out = nullptr;
         FarList none{};
-        PhaseScope ph(PH_LOOKUP, s);
+        PhaseScope ph(PH_LOOKUP, s, timed);
         st = launch_k_pass(lq, kind, H_NONE, vector_ok(lq, kind, false), none, 0, s);
         q.label_in = lq.label_out;
     }
@@ -2276,23 +2277,63 @@ static sinet_status run_window(const PassParams& p, uint32_t kind, int accumulat
     q.dst_inst = nullptr;
     const WinArgs a = win_carve(ws, q, P, accumulate);
     if (st == SINET_OK) {
-        PhaseScope ph(PH_INDEX, s);
+        PhaseScope ph(PH_INDEX, s, timed);
         st = win_launch_bounds(a, s);
     }
     if (st == SINET_OK) {
-        PhaseScope ph(PH_STAGE1, s);
+        PhaseScope ph(PH_STAGE1, s, timed);
         st = win_launch_main(a, s);
     }
     if (st == SINET_OK) {
-        PhaseScope ph(PH_STAGE2, s);
+        PhaseScope ph(PH_STAGE2, s, timed);
         st = win_launch_fixup(a, s);
     }
     if (st == SINET_OK) {
-        PhaseScope ph(PH_FAR, s);
+        PhaseScope ph(PH_FAR, s, timed);
         st = win_launch_far(a, s);
     }
+    return st;
+}
+
+static size_t window_ws_total(const PassParams& p, uint32_t kind, uint32_t P) {
+    const bool lookup = kind != KK_LABEL_IN;
+    return win_ws_bytes(p.n, P) + (lookup && !p.label_out ? al256(p.n) : 0);
+}
+
+static sinet_status run_window(const PassParams& p, uint32_t kind, int accumulate, hipStream_t s) {
+    const uint32_t P = win_pieces(p.n);
+    void* ws = nullptr;
+    sinet_status st = ws_alloc(&ws, window_ws_total(p, kind, P), s);
+    if (st != SINET_OK) return st;
+    st = run_window_in(p, kind, accumulate, s, ws, P, true);
     const sinet_status st2 = ws_free(ws, s);
     return st != SINET_OK ? st : st2;
+}
+
+// The histogram of run_hist with its workspace taken from `scratch` (bytes
+// long) instead of allocated: the private pass for small windows (no
+// workspace), else the sliding-window reduce with as many pieces as fit.
+// Records no timing events.
+sinet_status run_hist_in(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s,
+                         void* scratch, size_t bytes) {
+    const uint32_t kind = (mode & PASS_LABEL_IN) ? (uint32_t)KK_LABEL_IN : p.t.kind;
+    if (p.n == 0) return SINET_OK;
+    if (hist_strategy(p.t, kind, p.n_bins, p.n) == H_PRIVATE) {
+        sinet_status st = SINET_OK;
+        if (!accumulate) {
+            st = launch_zero(p.count, 4ull * p.n_bins, s);
+            if (st == SINET_OK) st = launch_zero(p.hbytes, 4ull * p.n_bins, s);
+            if (st != SINET_OK) return st;
+        }
+        FarList none{};
+        return launch_k_pass(p, kind, H_PRIVATE, vector_ok(p, kind, true), none,
+                             12ull * 4 * p.n_bins + 8, s);
+    }
+    uint32_t P = win_pieces(p.n);
+    while (P > 1 && window_ws_total(p, kind, P) > bytes) P = P * 3 / 4;
+    if (window_ws_total(p, kind, P) > bytes)
+        return fail(SINET_ERR_INVALID_ARG, "input too large for the static scratch");
+    return run_window_in(p, kind, accumulate, s, scratch, P, false);
 }
 
 sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s) {

@@ -213,6 +213,9 @@ sinet_status check_hip(hipError_t e, const char* what);
 
 // api.cpp
 sinet_status check_usable(const sinet_table* t);
+sinet_status pipeline_prepare(const sinet_table* t, const sinet_columns* cols, const sinet_window* win,
+                              uint8_t* label, sinet_hist* out, int accumulate, hipStream_t stream,
+                              PassParams* p, bool* done);
 sinet_status check_window(const sinet_window* w);
 DevTable label_view(const sinet_table* t, bool label_only);
 
@@ -230,6 +233,9 @@ sinet_status launch_pass(const PassParams& p, uint32_t mode, hipStream_t s);
 sinet_status launch_zero(unsigned long long* p, uint64_t n_words, hipStream_t s);
 // histogram passes (labels computed or given) with the strategy chosen per window
 sinet_status run_hist(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s);
+// run_hist with its workspace in `scratch` (bytes long), nothing allocated
+sinet_status run_hist_in(const PassParams& p, uint32_t mode, int accumulate, hipStream_t s,
+                         void* scratch, size_t bytes);
 // phase timing of run_hist (event pairs on the launch stream)
 enum TimedPhase { PH_LOOKUP = 0, PH_STAGE1, PH_INDEX, PH_STAGE2, PH_FAR, PH_COUNT };
 sinet_status timing_enable(int on);
