@@ -14,13 +14,18 @@ Forms timed on the same resident day (the first is the headline value):
   bsearch      plain binary search over the interval boundaries in global memory
   bsearch_lds  binary search with the top levels (sampled boundaries) in LDS
   trie         16-8-8 multibit trie
-  pla          learned: error-bounded piecewise-linear model, window search in the
-               LDS sampled boundaries, then the boundary leaf
-  mlp          learned: 1-16-1 ReLU MLP, same window search
+  pla          learned: error-bounded piecewise-linear model (about 7,700 segments,
+               max error 6): one aligned 16-boundary window per address
+  pla256       learned: 256 equal-count PLA segments, bounded search in the LDS
+               sampled boundaries, then the boundary leaf
+  mlp          learned: 1-16-1 ReLU MLP, same bounded search
   (every form but plain runs its own search for every address)
-  batched      the day cut into time-ordered streams, one graph launch
-               (table with the learned PLA and the in/out index: labels from the index)
-  batched_pla  the same with the learned PLA answering every lookup
+  batched_inout  the day cut into time-ordered streams, one graph launch, labels from
+               the in/out index (no model)
+  batched_pla  the same streams with the learned PLA answering every lookup
+The plain, search and learned forms reduce with the sliding window (a
+lookup pass stores the labels, then the window pass bins them); the batched
+forms with the two-stage records of the batch plan.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5|4|2|3]
                     [--forms plain,bsearch,...] [--no-cpu]
@@ -34,6 +39,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -45,7 +51,7 @@ METRIC = "sessions/sec classify+histogram on 1 GPU, % HBM roofline; learned vs p
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SESSION = 21   # ts 4 + src 4 + dst 4 + bytes 8 read, label 1 written
 BYTES_PER_BIN = 64       # 4 labels x (count 8 + bytes 8) written once
-DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,mlp,batched,batched_pla"
+DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,pla256,mlp,batched_inout,batched_pla"
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of the
 # plain form on the default day, scaled by the counters of a plain copy
 # (read x2.000, write x1.000)
@@ -98,10 +104,10 @@ def parse():
 
 
 def time_calls(torch, fn, steps, warmup, sinet=None):
-    """Average and minimum device ms per call from HIP events recorded on the
+    """Median and minimum device ms per call from HIP events recorded on the
     stream the library launches on (torch's current stream), host wall ms per
-    call over the timed loop, and (when sinet is given) the library's own
-    per-phase event timing summed over the timed calls."""
+    call over the timed loop, (when sinet is given) the library's own
+    per-phase event timing summed over the timed calls, and the mean ms."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -121,8 +127,10 @@ def time_calls(torch, fn, steps, warmup, sinet=None):
     if sinet is not None:
         phases = sinet.timing_read()
         sinet.timing_enable(False)
-    dev = [a.elapsed_time(b) for a, b in evs]
-    return sum(dev) / len(dev), min(dev), wall * 1e3 / steps, phases
+    dev = sorted(a.elapsed_time(b) for a, b in evs)
+    k = len(dev)
+    med = dev[k // 2] if k % 2 else 0.5 * (dev[k // 2 - 1] + dev[k // 2])
+    return med, dev[0], wall * 1e3 / steps, phases, sum(dev) / k
 
 
 def copy_ceiling(torch, gb=4.0, reps=10):
@@ -132,31 +140,39 @@ def copy_ceiling(torch, gb=4.0, reps=10):
     n = int(gb * 1e9) // 16
     x = torch.empty(n, 2, dtype=torch.int64, device="cuda")
     y = torch.empty_like(x)
-    _, ms, _, _ = time_calls(torch, lambda: y.copy_(x), reps, 2)
+    _, ms, _, _, _ = time_calls(torch, lambda: y.copy_(x), reps, 2)
     del x, y
     return 2 * 16 * n / (ms * 1e-3) / 1e9
 
 
 def kernel_roofline(phases, n, n_bins, steps, workload):
     """Roofline of the dominant kernel of the step from the library's phase
-    events over the timed calls: the stage-1 kernel (read ts/src/dst/bytes,
-    20 B, and write the label, 1 B, per session) or the stage-2 kernel (write
-    every bin once, 64 B per bin), whichever takes longer."""
+    events over the timed calls.  Sliding-window reduce: the lookup pass
+    (read src/dst, 8 B, write the label, 1 B, per session) or the window pass
+    (read ts, bytes and label, 13 B per session, write every bin once, 64 B
+    per bin).  Records reduce: stage 1 (21 B per session fused with the
+    lookup, else 13 B) or stage 2 (64 B per bin).  Whichever takes longer."""
     if phases is None or phases["stage1_launches"] == 0:
         return None
     launches = phases["stage1_launches"]
     per_step = launches / steps          # launches of each kernel in one step
     cand = []
-    # the fused stage 1 carries the whole per-session traffic; after a
-    # separate lookup pass it reads ts, bytes and the stored label (13 B)
-    fused = phases["lookup_ms"] == 0.0
-    cand.append(("k_stage1", phases["stage1_ms"] / launches,
-                 (BYTES_PER_SESSION if fused else 13) * n / per_step))
-    if phases["stage2_ms"] > 0:
-        cand.append(("k_stage2", phases["stage2_ms"] / launches, BYTES_PER_BIN * n_bins / per_step))
-    if not fused:
+    if phases.get("window_calls", 0):
+        cand.append(("k_window", phases["stage1_ms"] / launches,
+                     (13 * n + BYTES_PER_BIN * n_bins) / per_step))
         cand.append(("k_pass (lookup, labels stored)", phases["lookup_ms"] / launches,
                      9 * n / per_step))
+    else:
+        # the fused stage 1 carries the whole per-session traffic; after a
+        # separate lookup pass it reads ts, bytes and the stored label (13 B)
+        fused = phases["lookup_ms"] == 0.0
+        cand.append(("k_stage1", phases["stage1_ms"] / launches,
+                     (BYTES_PER_SESSION if fused else 13) * n / per_step))
+        if phases["stage2_ms"] > 0:
+            cand.append(("k_stage2", phases["stage2_ms"] / launches, BYTES_PER_BIN * n_bins / per_step))
+        if not fused:
+            cand.append(("k_pass (lookup, labels stored)", phases["lookup_ms"] / launches,
+                         9 * n / per_step))
     name, ms, alg = max(cand, key=lambda c: c[1])
     achieved = alg / (ms * 1e-3) / 1e9
     traffic = measured_traffic(name, workload)
@@ -183,23 +199,66 @@ def measured_traffic(kernel, workload):
     return rec["bytes"]
 
 
-def cpu_baseline(wl, cols, sinet, sample: int):
-    """The C oracle (single thread, per-length hash) on a contiguous sample of
-    the same day; generation and copies excluded."""
-    import oracle
-    n = min(sample, wl.n)
+def cpu_baseline(wl, cols, sinet, sample: int, gpu=None):
+    """The C oracle (per-length hash) as K single-threaded processes, one per
+    core this process may use (at most 16), on contiguous shards of a sample
+    of the same day; generation and copies excluded from the oracle seconds.
+    The shards' bins are added exactly and compared with the GPU's labels and
+    bins for the sample (bins only at least the jitter inside the sample's
+    time range, which no session outside it can reach)."""
+    import shutil
+    import tempfile
+
+    import numpy as np
+
+    from oracle import shards
+    k = shards.cores()
+    n = min(sample * k, wl.n)  # sample: sessions per core
     i0 = (wl.n - n) // 2
-    s = {k: (sinet.to_host_u64(v[i0:i0 + n]) if k == "bytes" else sinet.to_host_u32(v[i0:i0 + n]))
-         for k, v in cols.items()}
-    w = wl.window
-    t = time.perf_counter()
-    oracle.pipeline(wl.pbase, wl.plen, s["ts"], s["src"], s["dst"], s["bytes"], w.t0, w.width,
-                    w.n_bins, mode="hash")
-    dt = time.perf_counter() - t
-    return {"value": n / dt, "unit": "sessions/s", "cores": 1, "kind": "oracle",
-            "sample": f"sessions [{i0}, {i0 + n}) of the same day ({n} sessions, {dt:.1f} s): "
-                      f"per-length-hash longest-prefix match over {wl.n_prefix} prefixes, "
-                      f"{w.n_bins}-bin x 4-label histogram cleared and filled"}
+    base = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    tmp = tempfile.mkdtemp(prefix="sinet_cpu_", dir=base)
+    try:
+        d = shards.Columns.create(tmp, n)
+        step = 1 << 26
+        for a in range(0, n, step):
+            b = min(n, a + step)
+            d.write(a, **{c: (sinet.to_host_u64(cols[c][i0 + a:i0 + b]) if c == "bytes"
+                              else sinet.to_host_u32(cols[c][i0 + a:i0 + b]))
+                          for c in ("ts", "src", "dst", "bytes")})
+        w = wl.window
+        res = shards.run(d, wl.pbase, wl.plen, w.t0, w.width, w.n_bins, k=k)
+        cpu = shards.cpu_name()
+        check = {}
+        if gpu is not None:
+            import sinetgen
+            lab_gpu, cnt_gpu, byt_gpu = gpu
+            same_lab = bool(np.array_equal(d.map("label"), lab_gpu[i0:i0 + n].cpu().numpy()))
+            # bins no session outside [i0, i0 + n) can reach
+            t_lo = int(sinetgen.ts_base(wl, [i0])[0]) + wl.t_origin + wl.jitter + 1
+            t_hi = int(sinetgen.ts_base(wl, [i0 + n - 1])[0]) + wl.t_origin - wl.jitter - 1
+            b_lo = max(res["b_lo"], (t_lo - w.t0) // w.width + 1)
+            b_hi = min(res["b_lo"] + res["count"].shape[1], (t_hi - w.t0) // w.width)
+            same_bins = None
+            if b_hi > b_lo:
+                o = b_lo - res["b_lo"]
+                ec = res["count"][:, o:o + b_hi - b_lo]
+                eb = res["bytes"][:, o:o + b_hi - b_lo]
+                same_bins = bool(np.array_equal(sinet.to_host_u64(cnt_gpu[:, b_lo:b_hi]), ec) and
+                                 np.array_equal(sinet.to_host_u64(byt_gpu[:, b_lo:b_hi]), eb))
+            check = {"labels_equal_gpu": same_lab, "bins_equal_gpu": same_bins,
+                     "bins_checked": int(max(0, b_hi - b_lo)) * 4}
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    value = n / res["shard_s"]
+    out = {"value": value, "unit": "sessions/s", "cores": res["k"], "kind": "oracle",
+           "per_core": value / res["k"], "cpu": cpu["model"], "cpu_mhz": cpu["mhz"],
+           "wall_s": round(res["wall_s"], 2),
+           "sample": f"sessions [{i0}, {i0 + n}) of the same day ({n} sessions) in {res['k']} "
+                     f"contiguous shards, one oracle process per core (per-length-hash longest-prefix "
+                     f"match over {wl.n_prefix} prefixes, each shard's own bins), the slowest shard "
+                     f"{res['shard_s']:.1f} s; shard bins added exactly"}
+    out.update(check)
+    return out
 
 
 def day_streams(sinet, wl, cols, tab, k, label, out):
@@ -240,38 +299,55 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     out = sinet.new_hist(w.n_bins)
     results = {}
     for form in forms:
-        if form in ("batched", "batched_pla"):
-            # batched: labels from the in/out index of the PLA table;
+        if form in ("batched_inout", "batched_pla"):
+            # batched_inout: labels from the in/out index (no model);
             # batched_pla: labels from the learned PLA lookup itself
-            tab = sinet.Table(wl.pbase, wl.plen, kind="pla", inout_index=(form == "batched"))
-            rep = tab.train()
+            if form == "batched_inout":
+                tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch", inout_index=True)
+                rep = None
+            else:
+                tab = sinet.Table(wl.pbase, wl.plen, kind="pla", inout_index=False)
+                rep = tab.train()
             streams, outs = day_streams(sinet, wl, cols, tab, args.day_streams, label, out)
             tune = sinet.autotune(streams)
             plan = sinet.BatchPlan(streams, tune=tune)
             fn = plan.run
         else:
-            kind = "bsearch" if form in ("plain", "bsearch_lds") else form
+            kind = ("bsearch" if form in ("plain", "bsearch_lds") else
+                    "pla" if form == "pla256" else form)
             tab = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=(form == "plain"),
                               global_bsearch=(form == "bsearch"))
-            rep = tab.train() if kind in ("pla", "mlp") else None
+            rep = None
+            if kind == "mlp":
+                rep = tab.train()
+            elif kind == "pla":
+                rep = tab.train(segments=256) if form == "pla256" else tab.train()
             fn = (lambda t=tab: sinet.pipeline(t, cols["ts"], cols["src"], cols["dst"],
                                                cols["bytes"], w.t0, w.width, w.n_bins,
                                                label=label, out=out))
-        ms, ms_min, wall, phases = time_calls(torch, fn, args.steps, args.warmup,
-                                              None if form.startswith("batched") else sinet)
+        ms, ms_min, wall, phases, ms_mean = time_calls(torch, fn, args.steps, args.warmup,
+                                                       None if form.startswith("batched") else sinet)
         info = tab.info()
         results[form] = {"sessions_per_s": wl.n / (ms * 1e-3), "ms_per_step": ms, "ms_min": ms_min,
-                         "wall_ms": wall, "kind": sinet.KIND_NAMES[info.kind],
-                         "inout_index": bool(info.inout_index) and form in ("plain", "batched"),
-                         "m": int(info.m), "max_err": int(info.max_err),
-                         "segments": int(info.segments), "fallbacks": int(info.fallbacks),
-                         "train_ms": None if rep is None else round(rep.train_ms, 3)}
+                         "ms_mean": ms_mean, "wall_ms": wall, "kind": sinet.KIND_NAMES[info.kind],
+                         "inout_index": bool(info.inout_index) and form in ("plain", "batched_inout"),
+                         "m": int(info.m)}
+        if sinet.KIND_NAMES[info.kind] in ("pla", "mlp"):
+            e = int(info.max_err)
+            results[form].update({
+                "max_err": e, "segments": int(info.segments), "fallbacks": int(info.fallbacks),
+                # boundaries the bounded search may look at, and its probes (binary search
+                # over them; a window of at most 16 is one aligned 16-boundary read)
+                "search_window": 2 * e + 1,
+                "probes": 1 if 2 * e + 1 <= 16 else math.ceil(math.log2(2 * e + 2)),
+                "train_ms": None if rep is None else round(rep.train_ms, 3)})
         if phases is not None:
             results[form]["phases_ms_per_step"] = {
                 k[:-3]: phases[k] / args.steps
                 for k in ("lookup_ms", "stage1_ms", "index_ms", "stage2_ms", "far_ms")}
             results[form]["_phases"] = phases
         if form.startswith("batched"):
+            results[form]["reduce"] = "records (batch plan)"
             results[form]["tune"] = {"block": tune.block, "chunk": tune.chunk, "grid": tune.grid}
             results[form]["streams"] = len(streams)
             del plan, streams, outs
@@ -304,8 +380,14 @@ def bench_day(args, torch, sinet, sinetgen, gg):
     for k, v in results.items():
         line["forms"][k]["hbm_frac"] = alg_bytes / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     if not args.no_cpu:
-        sample = args.cpu_sample or (60_000_000 if wl.n_prefix <= 4096 else 40_000_000)
-        line["cpu_baseline"] = cpu_baseline(wl, cols, sinet, sample)
+        # the plain form's labels and bins, for the check
+        tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch", inout_index=True)
+        sinet.pipeline(tab, cols["ts"], cols["src"], cols["dst"], cols["bytes"], w.t0,
+                       w.width, w.n_bins, label=label, out=out)
+        torch.cuda.synchronize()
+        del tab
+        sample = args.cpu_sample or 25_000_000
+        line["cpu_baseline"] = cpu_baseline(wl, cols, sinet, sample, gpu=(label, out[0], out[1]))
     return line
 
 
@@ -335,8 +417,8 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
 
     n = sum(wl.n for wl in streams_wl)
     bins = sum(wl.window.n_bins for wl in streams_wl)
-    ms_b, min_b, _, _ = time_calls(torch, plan.run, args.steps, args.warmup)
-    ms_p, min_p, _, _ = time_calls(torch, per_stream, args.steps, args.warmup)
+    ms_b, min_b, _, _, _ = time_calls(torch, plan.run, args.steps, args.warmup)
+    ms_p, min_p, _, _, _ = time_calls(torch, per_stream, args.steps, args.warmup)
     alg_bytes = BYTES_PER_SESSION * n + BYTES_PER_BIN * bins
     achieved = alg_bytes / (ms_b * 1e-3) / 1e9
     line = {
@@ -358,20 +440,24 @@ def bench_batch(args, torch, sinet, sinetgen, gg):
                                        "sessions_per_s": n / (ms_p * 1e-3)}},
     }
     if not args.no_cpu:
-        # whole streams in order until about 10 s of oracle time
-        tot_n, tot_s, used = 0, 0.0, 0
+        # whole streams in order, each in shards over the cores, until about
+        # 10 s of oracle time
+        tot_n, tot_s, used, k = 0, 0.0, 0, 1
         for wl, c, *_ in built:
             r = cpu_baseline(wl, c, sinet, wl.n)
+            k = r["cores"]
             tot_n += wl.n
             tot_s += wl.n / r["value"]
             used += 1
             if tot_s > 10.0:
                 break
-        line["cpu_baseline"] = {"value": tot_n / tot_s, "unit": "sessions/s", "cores": 1,
-                                "kind": "oracle",
+        line["cpu_baseline"] = {"value": tot_n / tot_s, "unit": "sessions/s", "cores": k,
+                                "kind": "oracle", "per_core": tot_n / tot_s / k,
+                                "cpu": r["cpu"], "cpu_mhz": r["cpu_mhz"],
                                 "sample": f"the first {used} of the {len(built)} streams, whole "
-                                          f"({tot_n} sessions, {tot_s:.1f} s), each with its own "
-                                          "prefix table, window and bins"}
+                                          f"({tot_n} sessions, {tot_s:.1f} s of the slowest shards), "
+                                          f"each in {k} shards with its own prefix table, window "
+                                          "and bins"}
     return line
 
 
@@ -394,7 +480,7 @@ def bench_parse(args, torch, sinet, sinetgen, gg):
     def step():
         sinet.parse_sessions(dev, stext.ORIGIN_DAYS, capacity=n_lines)
 
-    ms, ms_min, wall, _ = time_calls(torch, step, args.steps, args.warmup)
+    ms, ms_min, wall, _, _ = time_calls(torch, step, args.steps, args.warmup)
     alg = dev.numel() + 20 * n_lines  # the text read once, the columns written once
     achieved = alg / (ms * 1e-3) / 1e9
     workload = f"parse-{dev.numel() / 1e9:.1f}GB-{n_lines}lines"
@@ -444,7 +530,7 @@ def bench_rebin(args, torch, sinet, sinetgen, gg):
         sinet.rebin(c, factor, out=oc)
         sinet.rebin(b, factor, out=ob)
 
-    ms, ms_min, wall, _ = time_calls(torch, step, args.steps, args.warmup)
+    ms, ms_min, wall, _, _ = time_calls(torch, step, args.steps, args.warmup)
     alg = 2 * 8 * 4 * w.n_bins  # every millisecond bin read once
     achieved = alg / (ms * 1e-3) / 1e9
     line = {
@@ -577,7 +663,7 @@ def bench_watch(args, torch, sinet, sinetgen, gg):
         sinet.watch_histogram(tab, cols["ts"], cols["src"], cols["dst"], cols["bytes"], t0, width,
                               n_bins, n_keys, out=out)
 
-    ms, ms_min, wall, ph = time_calls(torch, step, args.steps, args.warmup, sinet=sinet)
+    ms, ms_min, wall, ph, _ = time_calls(torch, step, args.steps, args.warmup, sinet=sinet)
     addrs = torch.from_numpy(wlist.addrs.view(np.int32)).cuda()
     ls, ld = torch.isin(cols["src"], addrs), torch.isin(cols["dst"], addrs)
     matched = int((ls | ld).sum())
@@ -639,7 +725,7 @@ def main():
         x = torch.ones(n, 2, dtype=torch.int64, device="cuda")
         y = torch.empty_like(x)
         torch.cuda.synchronize()
-        ms, _, _, _ = time_calls(torch, lambda: y.copy_(x), max(1, args.steps), 1)
+        ms, _, _, _, _ = time_calls(torch, lambda: y.copy_(x), max(1, args.steps), 1)
         print(json.dumps({"copy_bytes_each_way": 16 * n, "ms": ms,
                           "gbs_read_plus_write": 32 * n / (ms * 1e-3) / 1e9}), flush=True)
         return

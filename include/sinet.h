@@ -424,6 +424,7 @@ typedef struct {
     double far_ms;
     uint64_t calls;     /* timed sinet_histogram / sinet_pipeline calls */
     uint64_t stage1_launches;  /* stage-1 (or private-pass, or window) launches among them */
+    uint64_t window_calls;     /* calls (pieces of calls) reduced by the sliding window */
 } sinet_timing;
 
 /* on != 0: start timing every later sinet_histogram / sinet_pipeline call of

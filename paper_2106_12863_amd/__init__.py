@@ -75,7 +75,8 @@ class Stream(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("lookup_ms", ctypes.c_double), ("stage1_ms", ctypes.c_double),
                 ("index_ms", ctypes.c_double), ("stage2_ms", ctypes.c_double),
-                ("far_ms", ctypes.c_double), ("calls", U64), ("stage1_launches", U64)]
+                ("far_ms", ctypes.c_double), ("calls", U64), ("stage1_launches", U64),
+                ("window_calls", U64)]
 
 
 def _sig(name, args, res=I32):

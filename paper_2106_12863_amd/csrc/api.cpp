@@ -699,8 +699,8 @@ sinet_status sinet_set_reduce(sinet_reduce mode) { return set_reduce((int)mode);
 sinet_status sinet_timing_read(sinet_timing* out) {
     if (!out) return fail(SINET_ERR_INVALID_ARG, "out is NULL");
     double ms[PH_COUNT];
-    uint64_t calls = 0, launches = 0;
-    const sinet_status st = timing_read(ms, &calls, &launches);
+    uint64_t calls = 0, launches = 0, window = 0;
+    const sinet_status st = timing_read(ms, &calls, &launches, &window);
     if (st != SINET_OK) return st;
     out->lookup_ms = ms[PH_LOOKUP];
     out->stage1_ms = ms[PH_STAGE1];
@@ -709,6 +709,7 @@ sinet_status sinet_timing_read(sinet_timing* out) {
     out->far_ms = ms[PH_FAR];
     out->calls = calls;
     out->stage1_launches = launches;
+    out->window_calls = window;
     return SINET_OK;
 }
 

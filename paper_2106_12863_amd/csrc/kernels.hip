@@ -1951,6 +1951,7 @@ std::mutex g_tm_mu;
 bool g_tm_on = false;
 std::vector<Mark> g_tm_marks;
 uint64_t g_tm_calls = 0;
+uint64_t g_tm_window = 0;
 
 class PhaseScope {
    public:
@@ -1994,6 +1995,11 @@ void count_timed_call() {
     if (g_tm_on) ++g_tm_calls;
 }
 
+void count_window_call() {
+    std::lock_guard<std::mutex> g(g_tm_mu);
+    if (g_tm_on) ++g_tm_window;
+}
+
 void drop_marks_locked() {
     for (const Mark& m : g_tm_marks) {
         (void)hipEventDestroy(m.a);
@@ -2001,6 +2007,7 @@ void drop_marks_locked() {
     }
     g_tm_marks.clear();
     g_tm_calls = 0;
+    g_tm_window = 0;
 }
 }  // namespace
 
@@ -2011,7 +2018,8 @@ sinet_status timing_enable(int on) {
     return SINET_OK;
 }
 
-sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches) {
+sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches,
+                         uint64_t* window_calls) {
     std::lock_guard<std::mutex> g(g_tm_mu);
     for (int k = 0; k < PH_COUNT; ++k) ms[k] = 0.0;
     *stage1_launches = 0;
@@ -2024,6 +2032,7 @@ sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_
         if (m.phase == PH_STAGE1) ++*stage1_launches;
     }
     *calls = g_tm_calls;
+    *window_calls = g_tm_window;
     return SINET_OK;
 }
 
@@ -2305,6 +2314,7 @@ static sinet_status run_window(const PassParams& p, uint32_t kind, int accumulat
     void* ws = nullptr;
     sinet_status st = ws_alloc(&ws, window_ws_total(p, kind, P), s);
     if (st != SINET_OK) return st;
+    count_window_call();
     st = run_window_in(p, kind, accumulate, s, ws, P, true);
     const sinet_status st2 = ws_free(ws, s);
     return st != SINET_OK ? st : st2;

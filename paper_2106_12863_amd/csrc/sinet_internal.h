@@ -240,7 +240,8 @@ sinet_status run_hist_in(const PassParams& p, uint32_t mode, int accumulate, hip
 enum TimedPhase { PH_LOOKUP = 0, PH_STAGE1, PH_INDEX, PH_STAGE2, PH_FAR, PH_COUNT };
 sinet_status timing_enable(int on);
 sinet_status set_reduce(int mode);
-sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches);
+sinet_status timing_read(double ms[PH_COUNT], uint64_t* calls, uint64_t* stage1_launches,
+                         uint64_t* window_calls);
 size_t part_ws_bytes(uint64_t n, uint32_t n_bins);
 PartWs part_ws_carve(void* base, uint64_t n, uint32_t n_bins);
 sinet_status run_partitioned(const PassParams& p, uint32_t kind, const PartWs& w, int accumulate,
