@@ -4,20 +4,22 @@
 // common case.
 //
 // Layout (u32 words):
-//   [0, 2 * 4096)  per group of 16 consecutive /16 blocks: the 2-bit states of
-//                  the 16 blocks (0 outside the union, 1 inside, 2 cut by a
-//                  union boundary and outside at its first address, 3 cut and
-//                  inside at its first address), then the number of cut
-//                  blocks in all earlier groups;
-//   slot           one 8-byte slot per cut block, in address order, plus a
-//                  pad slot: the block's union boundaries b (offsets 1..65535
-//                  inside the block) stored as b - 1, ascending, padded with
-//                  0xFFFF; a block with more than four boundaries instead holds
-//                  0xFFFF, its boundary count, and the u16 offset of its sorted
-//                  offsets in the overflow list;
+//   [0, 2 * 4096)  per group of 16 consecutive /16 blocks: one word with, in
+//                  bits 0..15, block k's membership at its first address and,
+//                  in bits 16..31, whether a union boundary cuts block k;
+//                  then the byte offset of the group's first cut block's
+//                  slot in the slot region (8 x the number of cut blocks in
+//                  all earlier groups);
+//   slot           one 8-byte slot per cut block, in address order (then a
+//                  zero pad slot): the block's union boundaries b (offsets
+//                  1..65535 inside the block) stored as b - 1, ascending,
+//                  padded with 0xFFFF; a block with more than four boundaries
+//                  instead holds 0xFFFF, its boundary count, and the u16
+//                  offset of its sorted offsets in the overflow list;
 //   list           the overflow list (u16 pairs).
 // The membership of a = (block << 16) | x in a cut block is its starting
-// state flipped once per boundary b <= x.
+// state flipped once per boundary b <= x, i.e. by the parity of the number of
+// stored offsets b - 1 < x.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,7 +50,7 @@ inline bool build_inout_index(const std::vector<uint32_t>& U, std::vector<uint32
     bool state = false;
     uint32_t cut = 0;
     for (uint64_t k = 0; k < 65536; ++k) {
-        if ((k & 15) == 0) groups[2 * (k >> 4) + 1] = cut;
+        if ((k & 15) == 0) groups[2 * (k >> 4) + 1] = 8 * cut;  // bytes into the slot region
         const uint64_t base = k << 16;
         while (u < U.size() && U[u] == base) {  // a boundary at the block's first address
             state = !state;
@@ -62,7 +64,7 @@ inline bool build_inout_index(const std::vector<uint32_t>& U, std::vector<uint32
         }
         uint32_t st = s0 ? 1u : 0u;
         if (u != u0) {
-            st |= 2u;
+            st |= 1u << 16;
             const size_t nb = u - u0;
             if (nb <= kIoSlotMax) {
                 uint32_t e[kIoSlotMax];
@@ -78,10 +80,10 @@ inline bool build_inout_index(const std::vector<uint32_t>& U, std::vector<uint32
             }
             ++cut;
         }
-        groups[2 * (k >> 4)] |= st << ((k & 15) * 2);
+        groups[2 * (k >> 4)] |= st << (k & 15);
     }
-    slots.push_back(0xFFFFFFFFu);  // pad slot: read, never used, by uncut blocks past the last cut
-    slots.push_back(0xFFFFFFFFu);
+    slots.push_back(0u);  // pad slot: read, never used, by uncut blocks past the last cut
+    slots.push_back(0u);
     io.assign(groups.begin(), groups.end());
     lay.slot = (uint32_t)io.size();
     io.insert(io.end(), slots.begin(), slots.end());
@@ -108,31 +110,41 @@ __host__ __device__ inline uint32_t io_count_le(const uint32_t* list, uint32_t o
 }
 
 // Membership (0/1) of N addresses.  io is 8-byte aligned.  The group and
-// slot reads of all N addresses are issued before any is used.
+// slot reads of all N addresses are issued before any is used.  Block k of a
+// group: in = bit k, cut = bit 16 + k; the slot of a cut block follows the
+// group's first slot by the cut blocks before k in the group.  Only the
+// parity of the boundaries <= x matters.
 template <int N>
 __host__ __device__ inline void inout_lookup(const uint32_t* io, uint32_t slot_off,
                                              uint32_t list_off, const uint32_t* a, uint32_t* in) {
     const uint2* grp = reinterpret_cast<const uint2*>(io);
     const uint2* slot = reinterpret_cast<const uint2*>(io + slot_off);
     uint2 g[N], s[N];
+    uint32_t t[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) g[q] = grp[a[q] >> 20];
-    uint32_t st[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-        const uint32_t sh = ((a[q] >> 16) & 15u) * 2;
-        st[q] = (g[q].x >> sh) & 3u;
-        const uint32_t cut_before = (g[q].x >> 1) & 0x55555555u & ((1u << sh) - 1u);
-        s[q] = slot[g[q].y + (uint32_t)__builtin_popcount(cut_before)];
+        const uint32_t k = (a[q] >> 16) & 15u;
+        t[q] = g[q].x >> k;                                   // bit 0: in, bit 16: cut
+#ifdef __HIP_DEVICE_COMPILE__
+        const uint32_t before = __builtin_amdgcn_ubfe(g[q].x, 16u, k);  // cut blocks before k
+#else
+        const uint32_t before = (g[q].x >> 16) & ((1u << k) - 1u);
+#endif
+        s[q] = *reinterpret_cast<const uint2*>(reinterpret_cast<const char*>(slot) + g[q].y +
+                                               8u * (uint32_t)__builtin_popcount(before));
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         const uint32_t x = a[q] & 0xFFFFu;
-        uint32_t c = ((s[q].x & 0xFFFFu) < x) + ((s[q].x >> 16) < x) + ((s[q].y & 0xFFFFu) < x) +
-                     ((s[q].y >> 16) < x);
-        if (st[q] >= 2u && (s[q].x & 0xFFFFu) == 0xFFFFu)  // more than four boundaries
-            c = io_count_le(io + list_off, s[q].y, s[q].x >> 16, x);
-        in[q] = (st[q] ^ ((st[q] >> 1) & c)) & 1u;
+        uint32_t odd = ((s[q].x & 0xFFFFu) < x) ^ ((s[q].x >> 16) < x) ^ ((s[q].y & 0xFFFFu) < x) ^
+                       ((s[q].y >> 16) < x);
+        // a slot marking a block with more than four boundaries (read also by
+        // uncut lanes whose next cut block it is; the cut bit below masks them)
+        if ((s[q].x & 0xFFFFu) == 0xFFFFu)
+            odd = io_count_le(io + list_off, s[q].y, s[q].x >> 16, x) & 1u;
+        in[q] = (t[q] ^ (odd & (t[q] >> 16))) & 1u;
     }
 }
 

@@ -530,7 +530,7 @@ __device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) 
 //             the block reduction wrote the bins; without: every session.
 // ---------------------------------------------------------------------------
 template <uint32_t KIND, int HM, bool VEC>
-__global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
+__device__ __forceinline__ void pass_body(const PassParams& p, const FarList& far) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint32_t used = 0;
     const LdsView v = stage_lds<KIND>(p.t, lds, &used);
@@ -625,6 +625,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
             }
         }
     }
+}
+
+template <uint32_t KIND, int HM, bool VEC>
+__global__ void __launch_bounds__(kMaxBlock) k_pass(PassParams p, FarList far) {
+    pass_body<KIND, HM, VEC>(p, far);
+}
+
+// The label pass over the in/out index (the plain form's lookup): its 64 KB
+// of LDS lets two 1024-lane workgroups share a CU once the kernel fits in 64
+// VGPRs (eight waves per SIMD), twice the waves to hide the column loads.
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_pass_inout(PassParams p, FarList far) {
+    pass_body<KK_INOUT, H_NONE, true>(p, far);
 }
 
 // ---------------------------------------------------------------------------
@@ -1748,6 +1761,7 @@ using Stage1Fn = void (*)(PassParams, PartWs);
 
 template <uint32_t KIND>
 static PassFn pass_fn(int hm, bool vec) {
+    if (KIND == KK_INOUT && hm == H_NONE && vec) return k_pass_inout;
     switch (hm) {
         case H_NONE: return vec ? k_pass<KIND, H_NONE, true> : k_pass<KIND, H_NONE, false>;
         case H_ATOMIC: return vec ? k_pass<KIND, H_ATOMIC, true> : k_pass<KIND, H_ATOMIC, false>;
