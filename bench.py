@@ -356,6 +356,19 @@ def bench_day(args, torch, sinet, sinetgen, gg):
             del plan, streams, outs
         log(form, json.dumps(results[form]))
         del tab
+    if "plain" in results and wl.n < (1 << 32):
+        # the label runs (stable partition of the day's indices by label, per-wave
+        # ballots and mbcnt ranks) on the plain form's labels; not part of the step
+        ridx = torch.empty(wl.n, dtype=torch.int32, device="cuda")
+        rtot = torch.empty(4, dtype=torch.int64, device="cuda")
+        ms_r, min_r, _, _, _ = time_calls(torch, lambda: sinet.label_runs(label, ridx, rtot),
+                                          args.steps, args.warmup)
+        rb = 2 * wl.n + 4 * wl.n   # labels read by the count and scatter passes, indices written
+        results["plain"]["label_runs"] = {"ms_per_call": ms_r, "ms_min": min_r, "alg_bytes": rb,
+                                          "achieved_gbs": rb / (ms_r * 1e-3) / 1e9,
+                                          "totals": [int(x) for x in rtot.cpu().tolist()]}
+        log("label_runs", json.dumps(results["plain"]["label_runs"]))
+        del ridx
     head = forms[0]
     r = results[head]
     alg_bytes = BYTES_PER_SESSION * wl.n + BYTES_PER_BIN * w.n_bins

@@ -255,6 +255,24 @@ sinet_status sinet_discriminate(const sinet_table* t, const uint32_t* src, const
                                 uint64_t n, uint8_t* label, uint32_t* src_inst,
                                 uint32_t* dst_inst, hipStream_t stream);
 
+/* Label runs (section "Coordinated Batch Processing" and Fig. 3: the chunks
+ * are discriminated before the Map stage, so the later stages can take the
+ * sessions of one direction together): the stable partition of the session
+ * indices by label.  label: device u8[n] (its low two bits are the label, as
+ * sinet_discriminate writes them); idx: device u32[n], receives first every i
+ * with label 0 in increasing order, then label 1, 2, 3; totals: device u64[4],
+ * the number of sessions with each label (the run of label L starts at
+ * totals[0] + ... + totals[L-1]).  Each wave ranks its sessions within their
+ * label with a ballot per label and session slot and mbcnt, and takes its
+ * class totals from popcounts; a count pass, a scan over the workgroups'
+ * totals and a scatter pass place every index.  Caller-owned buffers; a workspace of 32 bytes per
+ * 262,144 sessions comes from the stream-ordered pool.  Errors: INVALID_ARG
+ * (totals NULL; label or idx NULL with n > 0), UNSUPPORTED (n >= 2^32: the
+ * indices are 32-bit), OUT_OF_MEMORY.  n == 0 zeroes totals.  Asynchronous on
+ * stream. */
+sinet_status sinet_label_runs(const uint8_t* label, uint64_t n, uint32_t* idx, uint64_t* totals,
+                              hipStream_t stream);
+
 /* Histogram of already labelled sessions (map to (label, bin), reduce by
  * addition).  accumulate == 0: outputs are cleared first; 1: added to (the
  * paper's merge of per-chunk results).  Errors: INVALID_ARG for null

@@ -65,6 +65,8 @@ def lib():
         L.or_rebin.restype = i32
         L.or_parse.argtypes = [P, u64, ctypes.c_int64, P, P, P, P, u64, P, P]
         L.or_parse.restype = i32
+        L.or_label_runs.argtypes = [P, u64, P, P]
+        L.or_label_runs.restype = i32
         L.or_endpoints.argtypes = [P, P, u64, P, P]
         L.or_endpoints.restype = ctypes.c_int64
         _lib = L
@@ -182,6 +184,20 @@ def watch(base, plen, ts, src, dst, nbytes, t0, width, n_bins, n_keys, inst=None
         raise ValueError("a key is not below n_keys")
     assert rc == 0
     return cnt, byt, drp
+
+
+def label_runs(label):
+    """Session indices partitioned by label, stably (uint32 [n]), and the
+    number of sessions with each label (uint64 [4])."""
+    label = np.ascontiguousarray(label, dtype=np.uint8)
+    n = label.shape[0]
+    idx = np.empty(n, np.uint32)
+    totals = np.zeros(4, np.uint64)
+    rc = lib().or_label_runs(_p(label), n, _p(idx), _p(totals))
+    if rc == 1:
+        raise ValueError("2^32 sessions or more")
+    assert rc == 0
+    return idx, totals
 
 
 def rebin(a, factor: int):

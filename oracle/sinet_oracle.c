@@ -470,3 +470,23 @@ int64_t or_endpoints(const uint32_t* base, const uint8_t* len, uint64_t n_prefix
     or_index_free(ix);
     return (int64_t)m;
 }
+
+/* Label runs (section "Coordinated Batch Processing", Fig. 3: the sessions of
+ * a chunk are discriminated before the Map stage): the stable partition of
+ * the session indices by label.  For L = 0, 1, 2, 3 in turn, every index i
+ * with (label[i] & 3) == L is appended in increasing order; totals[L] counts
+ * them.  n must be below 2^32 (the indices are 32-bit). */
+int or_label_runs(const uint8_t* label, uint64_t n, uint32_t* idx, uint64_t* totals) {
+    if (n >= (1ull << 32)) return 1;
+    uint64_t k = 0;
+    for (uint32_t L = 0; L < 4; ++L) {
+        totals[L] = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            if ((uint32_t)(label[i] & 3u) == L) {
+                idx[k++] = (uint32_t)i;
+                totals[L] += 1;
+            }
+        }
+    }
+    return 0;
+}

@@ -98,6 +98,7 @@ _sig("sinet_table_set_model", [P, P, P, P, P, U32, U32])
 _sig("sinet_table_destroy", [P])
 _sig("sinet_table_position", [P, P, U64, P, P])
 _sig("sinet_discriminate", [P, P, P, U64, P, P, P, P])
+_sig("sinet_label_runs", [P, U64, P, P, P])
 _sig("sinet_histogram", [P, P, P, U64, ctypes.POINTER(Window), ctypes.POINTER(Hist), I32, P])
 _sig("sinet_pipeline", [P, ctypes.POINTER(Columns), ctypes.POINTER(Window), P,
                         ctypes.POINTER(Hist), I32, P])
@@ -316,6 +317,25 @@ def discriminate(table: Table, src, dst, label=True, src_inst=False, dst_inst=Fa
     _check(_lib.sinet_discriminate(table.handle, _ptr(src), _ptr(dst), n, _ptr(lab), _ptr(si),
                                    _ptr(di), _stream(dev)), "sinet_discriminate")
     return lab, si, di
+
+
+def label_runs(label, idx=None, totals=None):
+    """Session indices partitioned by label, stably: (idx int32 storage of
+    uint32 [n], totals int64 storage of uint64 [4]).  label: device uint8."""
+    import torch
+    _dev_check(label)
+    n = label.numel()
+    _sized(label, 1, n, "label")
+    dev = label.device
+    if idx is None:
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+    if totals is None:
+        totals = torch.empty(4, dtype=torch.int64, device=dev)
+    _sized(idx, 4, n, "idx")
+    _sized(totals, 8, 4, "totals")
+    _check(_lib.sinet_label_runs(_ptr(label), n, _ptr(idx), _ptr(totals), _stream(dev)),
+           "sinet_label_runs")
+    return idx, totals
 
 
 def new_hist(n_bins: int, device="cuda"):

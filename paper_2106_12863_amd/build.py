@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libsinet.so")
-SOURCES = ["api.cpp", "kernels.hip", "learned.hip", "batch.hip", "stream.cpp", "rebin.hip", "parse.hip", "window.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "kernels.hip", "learned.hip", "batch.hip", "stream.cpp", "rebin.hip", "parse.hip", "window.hip", "noalloc.hip", "runs.hip"]
 ARCH = os.environ.get("SINET_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -71,6 +71,9 @@ def test_host_side_argument_errors():
     assert lib.sinet_pipeline(None, ctypes.byref(cols), ctypes.byref(w), None, ctypes.byref(h), 0,
                               None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_discriminate(None, P(16), P(16), 4, P(16), None, None, None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_label_runs(P(16), 4, P(16), None, None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_label_runs(None, 4, P(16), P(16), None) == sinet.ERR_INVALID_ARG
+    assert lib.sinet_label_runs(P(16), 1 << 32, P(16), P(16), None) == sinet.ERR_UNSUPPORTED
     assert lib.sinet_watch_histogram(None, ctypes.byref(cols), ctypes.byref(w), 3, ctypes.byref(h), 0,
                                      None) == sinet.ERR_INVALID_ARG
     assert lib.sinet_rebin(None, 4, 10, 2, P(16), None) == sinet.ERR_INVALID_ARG
