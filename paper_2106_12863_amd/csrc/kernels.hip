@@ -86,7 +86,28 @@ struct LdsView {
     const float* g;
     const uint32_t* radix;   // PLA: first segment of each radix bucket (u16 pairs)
     const float* w;          // MLP
+    uint32_t* queue;         // lookup pass of the interval kinds: this wave's search queue
 };
+
+// Entries of a wave's search queue: the searches of the 8 address slots (4
+// sessions) of the wave's 64 lanes.
+constexpr uint32_t kSearchQueue = 512;
+
+// Kinds whose lookup pass queues its searches: the binary searches, the trie
+// and the MLP (measured faster with the queue: their searches are issue-bound).
+// The PLA's searches are latency-bound (one window read per address) and were
+// measured slower queued (the window PLA 16.5 -> 23.6 ms per day, the
+// 256-segment PLA 24.3 -> 37.5 ms), so it keeps the direct path.
+__host__ __device__ constexpr bool queued_kind(uint32_t kind) {
+    return kind == KK_BSEARCH || kind == KK_TRIE || kind == KK_MLP;
+}
+
+// Orders this wave's LDS accesses: the ones before complete before the ones
+// after are issued (a wave's LDS requests are served in order; the clobber
+// keeps the compiler from moving accesses across).
+__device__ __forceinline__ void lds_wave_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
 
 // For each q: the last arr[i] <= a[q] among arr[0..n), given arr[0] <= a[q].
 template <int N>
@@ -284,7 +305,7 @@ __device__ __forceinline__ uint32_t scan_owner(const DevTable& t, const LdsView&
 // address.  Label-only lookups first consult the /16 filter: a block that no
 // boundary cuts is entirely in or entirely out, which answers most addresses
 // from LDS; only addresses in cut blocks run the table's search.
-template <uint32_t KIND, int N>
+template <uint32_t KIND, int N, bool QUEUE = false>
 __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, const uint32_t* a,
                                         bool want_code, uint32_t* in, uint32_t* code) {
     if constexpr (KIND == KK_INOUT) {
@@ -307,6 +328,53 @@ __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, con
                 st[q] = (v.filter[a[q] >> 20] >> (((a[q] >> 16) & 15u) * 2)) & 3u;
                 need |= (st[q] == 2u ? 1u : 0u) << q;
             }
+        }
+        if (QUEUE && v.queue && !want_code && t.filter_lds) {
+            // Wave-level compaction of the searches (section "Coordinated Batch
+            // Processing": the chunk is discriminated before the Map stage).  Only
+            // addresses in cut /16 blocks need one, about a third of them, yet a
+            // wave runs a slot's search whenever any of its lanes needs it.  The
+            // addresses that need one are ranked with a ballot and mbcnt per slot,
+            // queued in LDS, searched two per active lane per round (dense), and
+            // their membership bits read back from their queue entries.  Lanes may
+            // be inactive (the ragged last tile, the tail), so the active lanes are
+            // ranked among themselves.
+            const unsigned long long live = __ballot(1);
+            const uint32_t me = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u));
+            const uint32_t n_live = (uint32_t)__popcll(live);
+            uint32_t slot[N], cnt = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const bool nd = (need >> q) & 1u;
+                const unsigned long long m = __ballot(nd);
+                slot[q] = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (nd) v.queue[slot[q]] = a[q];
+                cnt += (uint32_t)__popcll(m);
+            }
+            if (cnt) {  // wave-uniform
+                lds_wave_sync();
+                for (uint32_t r = 0; r < cnt; r += 2 * n_live) {
+                    const uint32_t e0 = r + me, e1 = r + n_live + me;
+                    uint32_t x[2] = {e0 < cnt ? v.queue[e0] : 0u, e1 < cnt ? v.queue[e1] : 0u};
+                    uint32_t j[2] = {0u, 0u};
+                    intervals<KIND, 2>(t, v, x, j, (e0 < cnt ? 1u : 0u) | (e1 < cnt ? 2u : 0u));
+                    if (e0 < cnt) v.queue[e0] = (v.member[j[0] >> 5] >> (j[0] & 31)) & 1u;
+                    if (e1 < cnt) v.queue[e1] = (v.member[j[1] >> 5] >> (j[1] & 31)) & 1u;
+                }
+                lds_wave_sync();
+#pragma unroll
+                for (int q = 0; q < N; ++q)
+                    if ((need >> q) & 1u) in[q] = v.queue[slot[q]];
+                lds_wave_sync();  // read back before the queue is written again
+            }
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                if (st[q] < 2u) in[q] = st[q];
+                code[q] = 0;
+            }
+            return;
         }
         if (need) {
             uint32_t j[N];
@@ -361,12 +429,12 @@ __device__ __forceinline__ void account(const PassParams& p, const PrivHist& h, 
 }
 
 // Label of session i (scalar path); stores label / institutions when asked.
-template <uint32_t KIND>
+template <uint32_t KIND, bool QUEUE = false>
 __device__ __forceinline__ uint32_t label1(const PassParams& p, const LdsView& v, uint64_t i) {
     const uint32_t a[2] = {*glob(p.src + i), *glob(p.dst + i)};
     const bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
     uint32_t in[2], code[2];
-    lookups<KIND, 2>(p.t, v, a, wc, in, code);
+    lookups<KIND, 2, QUEUE>(p.t, v, a, wc, in, code);
     const uint32_t lab = in[0] | (in[1] << 1);
     if (p.label_out) *glob(p.label_out + i) = (uint8_t)lab;
     if (p.src_inst) *glob(p.src_inst + i) = code[0] ? p.t.inst[code[0] - 1] : SINET_NO_INST;
@@ -390,7 +458,7 @@ __device__ __forceinline__ void one_session(const PassParams& p, const LdsView& 
     if constexpr (KIND == KK_LABEL_IN) {
         lab = *glob(p.label_in + i) & 3u;
     } else {
-        lab = label1<KIND>(p, v, i);
+        lab = label1<KIND, HM == H_NONE && queued_kind(KIND)>(p, v, i);
     }
     if constexpr (HM != H_NONE) account<HM>(p, h, lab, *glob(p.ts + i), *glob(p.bytes + i), d);
 }
@@ -398,7 +466,7 @@ __device__ __forceinline__ void one_session(const PassParams& p, const LdsView& 
 // Labels of four consecutive sessions starting at i from their loaded source
 // and destination words (or the given labels); stores labels / institutions
 // when asked.
-template <uint32_t KIND>
+template <uint32_t KIND, bool QUEUE = false>
 __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView& v, uint64_t i,
                                              uint4 s, uint4 t, uint32_t l4, uint32_t lab[4]) {
     if constexpr (KIND == KK_LABEL_IN) {
@@ -409,7 +477,7 @@ __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView&
         const uint32_t a[8] = {s.x, s.y, s.z, s.w, t.x, t.y, t.z, t.w};
         const bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
         uint32_t in[8], code[8];
-        lookups<KIND, 8>(p.t, v, a, wc, in, code);
+        lookups<KIND, 8, QUEUE>(p.t, v, a, wc, in, code);
         uint32_t sc[4], dc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -440,7 +508,7 @@ __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView&
     }
 }
 
-template <uint32_t KIND>
+template <uint32_t KIND, bool QUEUE = false>
 __device__ __forceinline__ void labels4(const PassParams& p, const LdsView& v, uint64_t i,
                                         uint32_t lab[4]) {
     uint4 s = make_uint4(0, 0, 0, 0), t = s;
@@ -451,7 +519,7 @@ __device__ __forceinline__ void labels4(const PassParams& p, const LdsView& v, u
         s = gload4(p.src + i);
         t = gload4(p.dst + i);
     }
-    labels4_from<KIND>(p, v, i, s, t, l4, lab);
+    labels4_from<KIND, QUEUE>(p, v, i, s, t, l4, lab);
 }
 
 template <uint32_t KIND, int HM>
@@ -468,7 +536,7 @@ __device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView
         return;
     }
     uint32_t lab[4];
-    labels4<KIND>(p, v, i, lab);
+    labels4<KIND, HM == H_NONE && queued_kind(KIND)>(p, v, i, lab);
     if constexpr (HM != H_NONE) {
         const uint4 ts = gload4(p.ts + i);
         const ulonglong2 b01 = gload2(p.bytes + i);
@@ -533,7 +601,10 @@ template <uint32_t KIND, int HM, bool VEC>
 __device__ __forceinline__ void pass_body(const PassParams& p, const FarList& far) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint32_t used = 0;
-    const LdsView v = stage_lds<KIND>(p.t, lds, &used);
+    LdsView v = stage_lds<KIND>(p.t, lds, &used);
+    if constexpr (HM == H_NONE && queued_kind(KIND)) {
+        if (p.queue_words) v.queue = lds + used + (threadIdx.x >> 6) * p.queue_words;
+    }
     PrivHist h{nullptr, nullptr};
     if constexpr (HM == H_PRIVATE) {
         used = (used + 1) & ~1u;
@@ -591,7 +662,8 @@ __device__ __forceinline__ void pass_body(const PassParams& p, const FarList& fa
                     const uint64_t g = tl * tile + threadIdx.x;
                     if (full(tl)) {
                         uint32_t lab[4];
-                        labels4_from<KIND>(p, v, g * 4, cs, cd, 0u, lab);
+                        labels4_from<KIND, HM == H_NONE && queued_kind(KIND)>(p, v, g * 4, cs, cd,
+                                                                              0u, lab);
                     } else if (g * 4 < p.n) {
                         for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
                             one_session<KIND, HM>(p, v, h, i, d);
@@ -1843,16 +1915,30 @@ static sinet_status launch_k_pass(const PassParams& p, uint32_t kind, int hm, bo
                                   const FarList& far, size_t extra_lds, hipStream_t s) {
     PassFn fn = pick_pass(kind, hm, vec);
     if (!fn) return fail(SINET_ERR_UNSUPPORTED, "no kernel for this lookup kind");
-    const size_t lds = (kind == KK_LABEL_IN ? 0 : p.t.lds_bytes) + extra_lds + 8;
+    size_t lds = (kind == KK_LABEL_IN ? 0 : p.t.lds_bytes) + extra_lds + 8;
     if (lds > 160 * 1024) return fail(SINET_ERR_UNSUPPORTED, "table needs more LDS than a CU has");
     const int block = lds > 40 * 1024 ? 1024 : 256;
+    // the lookup pass of the queued kinds queues its searches per wave when
+    // the queues fit beside the table (labels only: positions and institution
+    // ids take the direct path)
+    PassParams q = p;
+    q.queue_words = 0;
+    // (the binary search over all boundaries in global memory, one leaf, is
+    // latency-bound like the PLA and keeps the direct path)
+    const bool global_search = kind == KK_BSEARCH && p.t.n_top <= 1;
+    if (hm == H_NONE && queued_kind(kind) && !global_search && !p.pos_out && !p.src_inst &&
+        !p.dst_inst &&
+        lds + (size_t)(block / 64) * kSearchQueue * 4 <= 160 * 1024) {
+        q.queue_words = kSearchQueue;
+        lds += (size_t)(block / 64) * kSearchQueue * 4;
+    }
     uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)fn, block, lds);
     if (!far.list) {
         const uint64_t tiles = ((p.n + 3) / 4 + block - 1) / block;
         if (grid > tiles) grid = tiles;
     }
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), lds, s, p, far);
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), lds, s, q, far);
     return check_hip(hipGetLastError(), "pass kernel launch");
 }
 

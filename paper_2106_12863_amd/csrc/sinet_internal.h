@@ -125,7 +125,8 @@ struct PassParams {
     uint32_t t0;
     uint32_t width;
     uint32_t n_bins;
-    uint32_t pad;
+    uint32_t queue_words;       // lookup pass: LDS words per wave for the search queue
+                                // (0: none; set at launch)
     uint64_t magic;             // ceil(2^64 / width) for width >= 2
 };
 
