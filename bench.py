@@ -34,6 +34,7 @@ forms with the two-stage records of the batch plan.
     python bench.py --parse    a 4 GB chunk of session text parsed into columns
     python bench.py --watch    watch-list histograms over the full day
                                (two synthetic lists, 1,177 hosts, 10-min bins)
+    python bench.py --crossover  record reduce vs sliding window over session counts
 """
 from __future__ import annotations
 
@@ -101,6 +102,8 @@ def parse():
                     help="the plain pipeline over the full day held in host memory (streamed)")
     ap.add_argument("--watch", action="store_true",
                     help="watch-list histograms over the full day instead of the default forms")
+    ap.add_argument("--crossover", action="store_true",
+                    help="the record reduce against the sliding window over session counts")
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="only run a plain device copy of this many GB (counter calibration)")
     return ap.parse_args()
@@ -728,6 +731,39 @@ def bench_watch(args, torch, sinet, sinetgen, gg):
     return line
 
 
+def bench_crossover(args, torch, sinet, sinetgen, gg):
+    """Median ms per pipeline call of the record reduce and of the sliding
+    window on days of the 1e8-session shape (1,024 prefixes) cut to n
+    sessions, with 86.4 M and 4 M 1-ms bins, and on 4e8 sessions of the
+    200,000-prefix day: where the automatic choice switches."""
+    cases = [(2, 4_200_000, 86_400_000), (2, 16_000_000, 86_400_000), (2, 33_000_000, 86_400_000),
+             (2, 100_000_000, 86_400_000), (2, 16_000_000, 4_000_000), (5, 400_000_000, 86_400_000)]
+    rows = []
+    for cfg, n, nb in cases:
+        wl = sinetgen.config(cfg, n=n)
+        cols = gg.alloc_and_fill(wl)
+        tab = sinet.Table(wl.pbase, wl.plen, kind="bsearch")
+        lab = torch.empty(n, dtype=torch.uint8, device="cuda")
+        out = sinet.new_hist(nb)
+        r = {"config": cfg, "n_sessions": n, "n_bins": nb}
+        try:
+            for red in ("records", "window"):
+                sinet.set_reduce(red)
+                ms, _, _, _, _ = time_calls(
+                    torch, lambda: sinet.pipeline(tab, cols["ts"], cols["src"], cols["dst"],
+                                                  cols["bytes"], 0, 1, nb, label=lab, out=out),
+                    args.steps, args.warmup)
+                r[red + "_ms"] = ms
+        finally:
+            sinet.set_reduce("auto")
+        log("crossover", json.dumps(r))
+        rows.append(r)
+        del cols, lab, out, tab
+        torch.cuda.empty_cache()
+    return {"metric": "ms per pipeline call, record reduce vs sliding window", "unit": "ms",
+            "higher_is_better": False, "data": "synthetic", "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -748,7 +784,9 @@ def main():
     import paper_2106_12863_amd as sinet
     import sinetgen
     import sinetgen.gpu as gg
-    if args.watch:
+    if args.crossover:
+        line = bench_crossover(args, torch, sinet, sinetgen, gg)
+    elif args.watch:
         line = bench_watch(args, torch, sinet, sinetgen, gg)
     elif args.host:
         line = bench_host(args, torch, sinet, sinetgen, gg)

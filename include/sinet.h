@@ -469,7 +469,8 @@ sinet_status sinet_timing_read(sinet_timing* out);
  *            sessions with the bins it touches in LDS and writes every bin
  *            once (labels are stored by a lookup pass first; about 1 byte
  *            of workspace per session plus 330 MB);
- *   AUTO     WINDOW from 2^22 sessions on, else RECORDS (the default).
+ *   AUTO     WINDOW from 2^28 sessions on, else RECORDS (the default; the
+ *            measured crossover of the two on a day of 1-ms bins).
  * Process-wide; takes effect for calls made after it returns.
  * Errors: INVALID_ARG (unknown mode). */
 typedef enum {

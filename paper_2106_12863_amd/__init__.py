@@ -654,7 +654,7 @@ REDUCES = {"auto": 0, "records": 1, "window": 2}
 def set_reduce(mode: str = "auto"):
     """Reduce of later histogram / pipeline calls: "records" (two-stage
     partition into 4-byte records), "window" (sliding window of bins in LDS
-    over labelled sessions) or "auto" (window from 2^22 sessions on)."""
+    over labelled sessions) or "auto" (window from 2^28 sessions on)."""
     if mode not in REDUCES:
         raise ValueError(f"reduce must be one of {sorted(REDUCES)}")
     _check(_lib.sinet_set_reduce(REDUCES[mode]), "sinet_set_reduce")
