@@ -1124,70 +1124,80 @@ __device__ __forceinline__ uint32_t line_skew(const unsigned long long* row) {
     return (uint32_t)(((128u - ((uintptr_t)row & 127u)) & 127u) >> 3);
 }
 
-// Write the block's bins and clear the accumulators it read.  Two bins per lane
-// with 16-byte stores.  Within every row the lanes start at the row's first
-// 128-byte line boundary inside the block and wrap around to the bins before
-// it, so each wave store covers whole lines and only the two lines a block
-// shares with its neighbours are written in part.  A row that starts 8 bytes
-// past a 16-byte boundary (n_bins odd, or an offset buffer) has an odd line
-// skew, so its pairs start at odd bins and stay 16-byte aligned; the lane
-// whose pair would wrap from the block's last bin to its first writes those
-// two bins with 8-byte stores instead.  Bins past the row's end are not
-// written.  A block without records (empty) writes zeros without touching the
-// accumulators, which are already clear.
-__device__ __forceinline__ void store_one(unsigned long long* q, unsigned long long x) {
-    __builtin_nontemporal_store(x, glob(q));
-}
-
-template <class A>
-__device__ __forceinline__ void stage2_write_row(A* acc, unsigned long long* row,
-                                                 uint64_t b0, uint32_t n_bins, uint32_t j, bool zeros,
-                                                 int accumulate) {
-    const uint32_t o = (line_skew(row) + 2 * j) & (kBlockBins - 1);
-    const bool wrap = o == kBlockBins - 1;     // only when the skew is odd
-    const uint32_t o2 = wrap ? 0u : o + 1;
-    unsigned long long x = 0ull, y = 0ull;
-    if (!zeros) {
-        x = (unsigned long long)acc[o];
-        y = (unsigned long long)acc[o2];
-        acc[o] = 0;
-        acc[o2] = 0;
-    }
-    if (!wrap && b0 + o + 1 < n_bins) {
-        unsigned long long* q = row + b0 + o;
-        if (accumulate) {
-            const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(q);
-            x += v.x;
-            y += v.y;
-        }
-        store_pair(q, x, y);
-        return;
-    }
-    if (b0 + o < n_bins) {
-        unsigned long long* q = row + b0 + o;
-        store_one(q, accumulate ? *q + x : x);
-    }
-    if (wrap && b0 < n_bins) {
-        unsigned long long* q = row + b0;
-        store_one(q, accumulate ? *q + y : y);
-    }
-}
-
+// Write the block's bins and clear the accumulators it read.  Two consecutive
+// bins per lane with 16-byte stores when the label rows are 16-byte aligned
+// (n_bins even), else one.  Within every row the lanes start at the row's
+// first 128-byte line boundary inside the block and wrap around to the bins
+// before it, so each wave store covers whole lines and only the two lines a
+// block shares with its neighbours are written in part.  On rows that are not
+// line-aligned (n_bins * 8 not a multiple of 128, or an offset buffer) wave
+// stores that straddle lines cost about a fifth of the write rate.  A block
+// without records (empty) writes zeros without touching the accumulators,
+// which are already clear.
 __device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t, bool empty) {
     const uint64_t b0 = (uint64_t)t.blk * kBlockBins;
-    const bool zeros = empty && !t.accumulate;
-    for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
-        const uint32_t lab = k / (kBlockBins / 2), j = k % (kBlockBins / 2);
-        const uint64_t row = (uint64_t)lab * t.n_bins;
-        stage2_write_row(sh.c + lab * kBlockBins, t.count + row, b0, t.n_bins, j, zeros, t.accumulate);
-        stage2_write_row(sh.b + lab * kBlockBins, t.hbytes + row, b0, t.n_bins, j, zeros, t.accumulate);
+    const bool pairs =
+        (t.n_bins & 1u) == 0 && (((uintptr_t)t.count | (uintptr_t)t.hbytes) & 15u) == 0;
+    if (pairs) {
+        const bool zeros = empty && !t.accumulate;
+        for (uint32_t k = threadIdx.x; k < 2 * kBlockBins; k += kStage2Block) {
+            const uint32_t lab = k / (kBlockBins / 2), j = k % (kBlockBins / 2);
+            const uint64_t row = (uint64_t)lab * t.n_bins;
+            // skews are even here: the rows are 16-byte aligned
+            const uint32_t oc = (line_skew(t.count + row) + 2 * j) & (kBlockBins - 1);
+            const uint32_t ob = (line_skew(t.hbytes + row) + 2 * j) & (kBlockBins - 1);
+            const uint32_t ec = lab * kBlockBins + oc, eb = lab * kBlockBins + ob;
+            ulonglong2 c = make_ulonglong2(0ull, 0ull), b = make_ulonglong2(0ull, 0ull);
+            if (!zeros) {
+                c = make_ulonglong2(sh.c[ec], sh.c[ec + 1]);
+                b = make_ulonglong2(sh.b[eb], sh.b[eb + 1]);
+                sh.c[ec] = 0;
+                sh.c[ec + 1] = 0;
+                sh.b[eb] = 0;
+                sh.b[eb + 1] = 0;
+            }
+            // n_bins even: bin + 1 is inside whenever bin is
+            if (b0 + oc < t.n_bins) {
+                unsigned long long* q = t.count + row + b0 + oc;
+                if (t.accumulate) {
+                    const ulonglong2 o = *reinterpret_cast<const ulonglong2*>(q);
+                    c.x += o.x;
+                    c.y += o.y;
+                }
+                store_pair(q, c.x, c.y);
+            }
+            if (b0 + ob < t.n_bins) {
+                unsigned long long* q = t.hbytes + row + b0 + ob;
+                if (t.accumulate) {
+                    const ulonglong2 o = *reinterpret_cast<const ulonglong2*>(q);
+                    b.x += o.x;
+                    b.y += o.y;
+                }
+                store_pair(q, b.x, b.y);
+            }
+        }
+    } else {
+        for (uint32_t k = threadIdx.x; k < 4 * kBlockBins; k += kStage2Block) {
+            const uint32_t lab = k / kBlockBins, j = k % kBlockBins;
+            const uint64_t row = (uint64_t)lab * t.n_bins;
+            const uint32_t oc = (line_skew(t.count + row) + j) & (kBlockBins - 1);
+            const uint32_t ob = (line_skew(t.hbytes + row) + j) & (kBlockBins - 1);
+            unsigned long long c = sh.c[lab * kBlockBins + oc], b = sh.b[lab * kBlockBins + ob];
+            sh.c[lab * kBlockBins + oc] = 0;
+            sh.b[lab * kBlockBins + ob] = 0;
+            if (b0 + oc < t.n_bins) {
+                unsigned long long* q = t.count + row + b0 + oc;
+                *q = t.accumulate ? *q + c : c;
+            }
+            if (b0 + ob < t.n_bins) {
+                unsigned long long* q = t.hbytes + row + b0 + ob;
+                *q = t.accumulate ? *q + b : b;
+            }
+        }
     }
 }
 
-// The persistent block loop; out(g) names where block g's bins go.  Its
-// barriers order LDS only (lds_barrier): a block's bin stores and the next
-// blocks' descriptor loads stay in flight across them, so a sparse block's
-// write overlaps the next block's record loads.
+// The persistent block loop; out(g) names where block g's bins go.
 template <class Out>
 __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, const Out& out) {
     const uint32_t tid = threadIdx.x;
@@ -1214,7 +1224,7 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
     }
     BlockOut cur = out(g);  // where the current block's bins go (found one block ahead)
     for (uint32_t d = 0; g < nb; g = gn, gn += G, d ^= 1u) {
-        lds_barrier();  // descriptors of g in buffer d, accumulators clear
+        __syncthreads();  // descriptors of g in buffer d, accumulators clear
         // in flight during this block: the next block's descriptors and the
         // segment range of the block after it
         const uint32_t nn = gn < nb ? min(n1 - n0, (uint32_t)kSegMax) : 0u;
@@ -1232,12 +1242,12 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
         // batches through the same buffer
         const uint32_t s0 = sh.s0[d], s1 = sh.s1[d];
         for (uint32_t sb = s0 + kSegMax; sb < s1; sb += kSegMax) {
-            lds_barrier();
+            __syncthreads();
             stage2_describe(w, sh, d, sb, min(s1 - sb, (uint32_t)kSegMax));
-            lds_barrier();
+            __syncthreads();
             stage2_segments(w, sh, d);
         }
-        lds_barrier();  // accumulation complete
+        __syncthreads();  // accumulation complete
         stage2_write(sh, cur, s0 == s1);
         if (gn < nb) {
             const uint32_t e = d ^ 1u;  // last read before this block's first barrier
