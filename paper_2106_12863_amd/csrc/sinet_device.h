@@ -27,10 +27,16 @@ __device__ __forceinline__ int clamp_pos(float pred, uint32_t m) {
 }
 
 // PLA line of one segment: c + g * (a - knot) in float32, round to nearest,
-// no contraction (the error bound is measured with exactly this arithmetic).
+// one rounding per operation (the error bound is measured with exactly this
+// arithmetic).  The operators are written out under the pragma: the
+// compiler fuses a product and a sum into one fma wherever contraction is
+// left on, including inside __fmul_rn / __fadd_rn, which are plain operators
+// in this toolchain.
 __device__ __forceinline__ float pla_eval(uint32_t knot, float c, float g, uint32_t a) {
+#pragma clang fp contract(off)
     const float d = __uint2float_rn(a - knot);
-    return __fadd_rn(c, __fmul_rn(g, d));
+    const float gd = g * d;
+    return c + gd;
 }
 
 // PLA prediction with the segment found by a full search over the knots.
@@ -40,16 +46,20 @@ __device__ __forceinline__ float pla_predict(const uint32_t* knot, const float* 
     return pla_eval(knot[s], c[s], g[s], a);
 }
 
-// MLP prediction: m * (b2 + sum_k w2_k relu(w1_k x + b1_k)), x = a / 2^32.
+// MLP prediction: m * (b2 + sum_k w2_k relu(w1_k x + b1_k)), x = a / 2^32,
+// one rounding per operation (no fma, as in pla_eval), accumulated in k order.
 __device__ __forceinline__ float mlp_predict(const float* w, float m_f, uint32_t a) {
-    float x = __fmul_rn(__uint2float_rn(a), 2.3283064365386963e-10f);
+#pragma clang fp contract(off)
+    const float x = __uint2float_rn(a) * 2.3283064365386963e-10f;
     float f = w[48];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        float z = __fadd_rn(__fmul_rn(w[k], x), w[16 + k]);
-        f = __fadd_rn(f, __fmul_rn(w[32 + k], fmaxf(z, 0.0f)));
+        const float wx = w[k] * x;
+        const float z = wx + w[16 + k];
+        const float t = w[32 + k] * fmaxf(z, 0.0f);
+        f = f + t;
     }
-    return __fmul_rn(f, m_f);
+    return f * m_f;
 }
 
 }  // namespace sinet
