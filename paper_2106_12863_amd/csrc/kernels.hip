@@ -93,13 +93,18 @@ struct LdsView {
 // sessions) of the wave's 64 lanes.
 constexpr uint32_t kSearchQueue = 512;
 
+// The window PLA queues the searches of two address slots at a time (128
+// entries per wave: the PLA's tables leave little LDS beside them).
+constexpr int kPlaGroup = 2;
+constexpr uint32_t kPlaQueue = 64u * kPlaGroup;
+
 // Kinds whose lookup pass queues its searches: the binary searches, the trie
-// and the MLP (measured faster with the queue: their searches are issue-bound).
-// The PLA's searches are latency-bound (one window read per address) and were
-// measured slower queued (the window PLA 16.5 -> 23.6 ms per day, the
-// 256-segment PLA 24.3 -> 37.5 ms), so it keeps the direct path.
+// and the MLP (measured faster with the queue: their searches are issue-bound),
+// and the window PLA, whose queued searches read each window with four lanes.
+// A PLA with a wider bound searches unqueued (the 256-segment PLA queued two
+// searches per lane was measured slower, 24.3 -> 37.5 ms per day).
 __host__ __device__ constexpr bool queued_kind(uint32_t kind) {
-    return kind == KK_BSEARCH || kind == KK_TRIE || kind == KK_MLP;
+    return kind == KK_BSEARCH || kind == KK_TRIE || kind == KK_MLP || kind == KK_PLA;
 }
 
 // Orders this wave's LDS accesses: the ones before complete before the ones
@@ -243,6 +248,122 @@ __device__ __forceinline__ void window_search_n(const DevTable& t, const uint32_
     }
 }
 
+// Lane index within the wave.
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Rank of this lane among the lanes set in m.
+__device__ __forceinline__ uint32_t rank_in(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// x of lane src (every lane active).
+__device__ __forceinline__ uint32_t from_lane(uint32_t src, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
+}
+
+// Sum over the four lanes of each quad, in every lane of the quad (DPP quad
+// permutations [1,0,3,2] then [2,3,0,1]; every lane active).
+__device__ __forceinline__ uint32_t quad_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+    return x;
+}
+
+// Membership bits of the addresses in cut /16 blocks by the window PLA, for a
+// wave whose 64 lanes are all active.  The window search's cost is the
+// memory pipeline's: unqueued, each address reads its 16-boundary window with
+// four 16-byte loads of its own lane, in waves where about a third of the
+// lanes need a search.  Here the addresses that need one, two slots at a time,
+// are ranked with a ballot and mbcnt and queued in LDS; each round gives one
+// queued address to every lane, which finds its segment, evaluates the line
+// and forms the window's first index; then each quad of lanes takes one
+// address per step (its address and window start moved over with
+// ds_bpermute), each lane loads and compares four of the 16 boundaries, and
+// the quad's counts are added with DPP.  One load instruction covers 16
+// windows.  The quad's first lane checks the bracket (falling back to the full
+// search, counted, as window_search_n does), reads the interval's membership
+// bit and writes it over the queue entry, from which the address's lane reads
+// it back.
+template <int N>
+__device__ __forceinline__ void pla_window_queued(const DevTable& t, const LdsView& v,
+                                                  const uint32_t* a, uint32_t need, uint32_t* in) {
+    const uint32_t lane = lane_id();
+    const int e = (int)t.max_err;
+#pragma unroll
+    for (int q0 = 0; q0 < N; q0 += kPlaGroup) {
+        uint32_t slot[kPlaGroup], cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kPlaGroup; ++k) {
+            const bool nd = (need >> (q0 + k)) & 1u;
+            const unsigned long long m = __ballot(nd);
+            slot[k] = cnt + rank_in(m);
+            if (nd) v.queue[slot[k]] = a[q0 + k];
+            cnt += (uint32_t)__popcll(m);
+        }
+        if (cnt == 0) continue;  // wave-uniform
+        lds_wave_sync();
+        for (uint32_t r = 0; r < cnt; r += 64) {
+            const uint32_t nr = min(cnt - r, 64u);  // entries this round (wave-uniform)
+            const bool mine = lane < nr;
+            const uint32_t x = mine ? v.queue[r + lane] : 0u;
+            uint32_t wb = 0;
+            if (mine) {
+                // radix bucket -> candidate segments -> last knot <= x -> line
+                const uint32_t rb = x >> (32 - t.radix_bits);
+                const uint32_t s0 = radix_entry(v.radix, rb), s1 = radix_entry(v.radix, rb + 1);
+                const uint32_t sg = s0 + upper_last(v.knot + s0, s1 - s0 + 1, x);
+                const int pp = clamp_pos(pla_eval(v.knot[sg], v.c[sg], v.g[sg], x), t.m);
+                wb = (uint32_t)max(pp - e, 0) & ~3u;
+            }
+            // the round's four steps of 16 addresses: every window load (and
+            // the boundary after each window, for the bracket check) is issued
+            // before any is used
+            uint32_t xx[4], bb[4], nx[4];
+            uint4 w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t src = 16u * k + (lane >> 2);
+                xx[k] = from_lane(src, x);
+                bb[k] = from_lane(src, wb);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t src = 16u * k + (lane >> 2);
+                w[k] = make_uint4(0u, 0u, 0u, 0u);
+                nx[k] = 0xFFFFFFFFu;
+                if (src < nr) {  // quad-uniform
+                    w[k] = *reinterpret_cast<const uint4*>(t.B + bb[k] + 4u * (lane & 3u));
+                    if ((lane & 3u) == 0u) nx[k] = t.B[bb[k] + 16u];  // in the padding at worst
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t src = 16u * k + (lane >> 2);
+                const uint32_t c = quad_sum((uint32_t)(w[k].x <= xx[k]) + (uint32_t)(w[k].y <= xx[k]) +
+                                            (uint32_t)(w[k].z <= xx[k]) + (uint32_t)(w[k].w <= xx[k]));
+                if (src < nr && (lane & 3u) == 0u) {
+                    bool ok = c >= 1u;
+                    if (c == 16u && bb[k] + 16u < t.m) ok = xx[k] < nx[k];
+                    uint32_t j = bb[k] + c - 1u;
+                    if (!ok) {
+                        atomicAdd(t.fallbacks, 1ull);
+                        j = upper_last(t.B, t.m, xx[k]);
+                    }
+                    j = min(j, t.m - 1);
+                    v.queue[r + src] = (v.member[j >> 5] >> (j & 31)) & 1u;
+                }
+            }
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int k = 0; k < kPlaGroup; ++k)
+            if ((need >> (q0 + k)) & 1u) in[q0 + k] = v.queue[slot[k]];
+        lds_wave_sync();  // read back before the queue is written again
+    }
+}
+
 // Interval index of each address (all kinds but SCAN).  Addresses whose bit
 // in `need` is clear are skipped (their j is left unspecified); skipped lanes
 // issue no memory requests.
@@ -329,7 +450,18 @@ __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, con
                 need |= (st[q] == 2u ? 1u : 0u) << q;
             }
         }
-        if (QUEUE && v.queue && !want_code && t.filter_lds) {
+        if constexpr (QUEUE && KIND == KK_PLA) {
+            if (v.queue && !want_code && t.filter_lds && t.pla_window && __ballot(1) == ~0ull) {
+                pla_window_queued<N>(t, v, a, need, in);
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    if (st[q] < 2u) in[q] = st[q];
+                    code[q] = 0;
+                }
+                return;
+            }
+        }
+        if (QUEUE && KIND != KK_PLA && v.queue && !want_code && t.filter_lds) {
             // Wave-level compaction of the searches (section "Coordinated Batch
             // Processing": the chunk is discriminated before the Map stage).  Only
             // addresses in cut /16 blocks need one, about a third of them, yet a
@@ -551,7 +683,7 @@ __device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView
 // Stage the table's hot arrays into LDS (layout chosen on the host).
 // Returns the view; *words receives the number of 32-bit words used.
 template <uint32_t KIND>
-__device__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) {
+__device__ __forceinline__ LdsView stage_lds(const DevTable& t, uint32_t* lds, uint32_t* words) {
     LdsView v{};
     uint32_t off = 0;
     auto copy = [&](const uint32_t* src, uint32_t n) -> const uint32_t* {
@@ -1936,11 +2068,11 @@ static sinet_status launch_k_pass(const PassParams& p, uint32_t kind, int hm, bo
     // (the binary search over all boundaries in global memory, one leaf, is
     // latency-bound like the PLA and keeps the direct path)
     const bool global_search = kind == KK_BSEARCH && p.t.n_top <= 1;
-    if (hm == H_NONE && queued_kind(kind) && !global_search && !p.pos_out && !p.src_inst &&
-        !p.dst_inst &&
-        lds + (size_t)(block / 64) * kSearchQueue * 4 <= 160 * 1024) {
-        q.queue_words = kSearchQueue;
-        lds += (size_t)(block / 64) * kSearchQueue * 4;
+    const uint32_t qw = kind == KK_PLA ? (p.t.pla_window ? kPlaQueue : 0u) : kSearchQueue;
+    if (hm == H_NONE && queued_kind(kind) && qw && !global_search && !p.pos_out && !p.src_inst &&
+        !p.dst_inst && lds + (size_t)(block / 64) * qw * 4 <= 160 * 1024) {
+        q.queue_words = qw;
+        lds += (size_t)(block / 64) * qw * 4;
     }
     uint64_t grid = (uint64_t)device_cu_count() * blocks_per_cu((const void*)fn, block, lds);
     if (!far.list) {

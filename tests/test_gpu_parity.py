@@ -581,6 +581,20 @@ def test_learned_forced_fallback_stays_exact(sinet, torch):
         torch.cuda.synchronize()
         assert np.array_equal(sinet.to_host_u32(pos).astype(np.int64), learned.positions(B, q))
         assert tab.info().fallbacks > 0
+        if kind == "pla":
+            # labels only: the lookup pass's queued window search (quads of
+            # lanes per window) with the same wrong bound, at every boundary
+            # and the address below it, and a ragged tail of unqueued waves
+            tl = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=False)
+            tl.set_model(pla=model, max_err=0)
+            assert tl.info().pla_window == 1
+            src = np.concatenate([B, B - 1, q[:7]]).astype(np.uint32)
+            dst = rng.permutation(src)
+            lab, _, _ = sinet.discriminate(tl, sinet.to_device_u32(src), sinet.to_device_u32(dst))
+            torch.cuda.synchronize()
+            elab, _, _ = oracle.classify(wl.pbase, wl.plen, src, dst)
+            assert np.array_equal(lab.cpu().numpy(), elab)
+            assert tl.info().fallbacks > 0
         # reloading with a measured bound restores exact, fallback-free PLA lookups
         if kind == "pla":
             tab2 = sinet.Table(wl.pbase, wl.plen, kind=kind)
