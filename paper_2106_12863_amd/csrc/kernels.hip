@@ -202,9 +202,10 @@ __device__ __forceinline__ void learned_search_n(const DevTable& t, const LdsVie
 // PLA window search (max_err = e <= kPlaWindowErr): the interval of a lies
 // within e of the rounded prediction p, so the 16 boundaries from
 // s = (p - e) rounded down to a multiple of 4 hold it.  They are read with
-// four aligned 16-byte loads (two addresses' windows in flight at once), and
-// j = s + (the number of them <= a) - 1.  A count of 0, or of 16 with
-// B[s + 16] <= a, means the bound was wrong: the full search answers, counted.
+// four aligned 16-byte loads, and B[s + 16] with them (two addresses'
+// windows in flight at once), and j = s + (the number of them <= a) - 1.  A
+// count of 0, or of 16 with B[s + 16] <= a, means the bound was wrong: the
+// full search answers, counted.
 template <int N>
 __device__ __forceinline__ void window_search_n(const DevTable& t, const uint32_t* a, const int* p,
                                                 uint32_t* j, uint32_t need) {
@@ -213,7 +214,7 @@ __device__ __forceinline__ void window_search_n(const DevTable& t, const uint32_
 #pragma unroll
     for (int q0 = 0; q0 < N; q0 += G) {
         uint4 w[G][4];
-        uint32_t s[G];
+        uint32_t s[G], nx[G];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             s[q] = (uint32_t)max(p[q0 + q] - e, 0) & ~3u;
@@ -221,9 +222,11 @@ __device__ __forceinline__ void window_search_n(const DevTable& t, const uint32_
                 const uint4* b4 = reinterpret_cast<const uint4*>(t.B + s[q]);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) w[q][v] = b4[v];
+                nx[q] = t.B[s[q] + 16u];  // for the bracket check (in the padding at worst)
             } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) w[q][v] = make_uint4(0u, 0u, 0u, 0u);
+                nx[q] = 0xFFFFFFFFu;
             }
         }
 #pragma unroll
@@ -237,7 +240,7 @@ __device__ __forceinline__ void window_search_n(const DevTable& t, const uint32_
                 c += (uint32_t)(w[q][v].x <= x) + (uint32_t)(w[q][v].y <= x) +
                      (uint32_t)(w[q][v].z <= x) + (uint32_t)(w[q][v].w <= x);
             bool ok = c >= 1u;
-            if (c == 16u && s[q] + 16u < t.m) ok = x < t.B[s[q] + 16u];
+            if (c == 16u && s[q] + 16u < t.m) ok = x < nx[q];
             uint32_t r = s[q] + c - 1u;
             if (!ok) {
                 atomicAdd(t.fallbacks, 1ull);
@@ -1642,6 +1645,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_batch_lookup(BatchArgs a) {
             for (uint32_t k = tid; k < kWords; k += blockDim.x) dst[k] = src[k];
             __syncthreads();
             v = stage_lds<KIND>(s_bs.p.t, lds, &used);  // ends with a barrier
+            // the window PLA's search queue, after the table (a.queue_words
+            // per wave when the launch made room for it)
+            if constexpr (KIND == KK_PLA)
+                v.queue = a.queue_words ? lds + used + (tid >> 6) * a.queue_words : nullptr;
             staged = si;
         }
         BatchStreamDev bs;
@@ -1670,7 +1677,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_batch_lookup(BatchArgs a) {
             }
             if (full(g)) {
                 uint32_t lab[4];
-                labels4_from<KIND>(p, v, g * 4, cs, cd, 0u, lab);
+                labels4_from<KIND, KIND == KK_PLA>(p, v, g * 4, cs, cd, 0u, lab);
             } else {
                 Dropped d{};
                 for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
@@ -2364,8 +2371,17 @@ sinet_status launch_batch_lookup(uint32_t kind, const BatchArgs& a, size_t lds, 
     if (lds + sizeof(BatchStreamDev) + 16 > 160 * 1024)
         return fail(SINET_ERR_UNSUPPORTED, "batch needs more LDS than a CU has");
     const int block = lds > 40 * 1024 ? kMaxBlock : 256;
+    // the window PLA's search queues (for a whole block of the largest size)
+    // when they fit beside the group's largest table
+    BatchArgs b = a;
+    b.queue_words = 0;
+    const size_t qbytes = (size_t)(kMaxBlock / 64) * kPlaQueue * 4;
+    if (kind == KK_PLA && lds + qbytes + sizeof(BatchStreamDev) + 16 <= 160 * 1024) {
+        b.queue_words = kPlaQueue;
+        lds += qbytes;
+    }
     if (grid == 0) grid = device_cu_count() * blocks_per_cu((const void*)fn, block, lds);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, b);
     return check_hip(hipGetLastError(), "batch lookup launch");
 }
 

@@ -181,7 +181,7 @@ struct BatchArgs {
     const uint64_t* chunk_base; // [n_streams + 1] first workspace chunk of each stream
     const uint32_t* block_base; // [n_streams + 1] first workspace block of each stream
     uint32_t priv_bins;         // largest private histogram (bins) of the group
-    uint32_t pad;
+    uint32_t queue_words;       // lookup pass: LDS words per wave for the window PLA's queue
 };
 
 struct ZeroJob {
