@@ -285,10 +285,10 @@ __device__ __forceinline__ uint32_t quad_sum(uint32_t x) {
 // address per step (its address and window start moved over with
 // ds_bpermute), each lane loads and compares four of the 16 boundaries, and
 // the quad's counts are added with DPP.  One load instruction covers 16
-// windows.  The quad's first lane checks the bracket (falling back to the full
-// search, counted, as window_search_n does), reads the interval's membership
-// bit and writes it over the queue entry, from which the address's lane reads
-// it back.
+// windows.  The lane at place k of a quad then finishes the quad's address of
+// step k: it checks the bracket (falling back to the full search, counted, as
+// window_search_n does), reads the interval's membership bit and writes it
+// over the queue entry, from which the address's lane reads it back.
 template <int N>
 __device__ __forceinline__ void pla_window_queued(const DevTable& t, const LdsView& v,
                                                   const uint32_t* a, uint32_t need, uint32_t* in) {
@@ -320,43 +320,54 @@ __device__ __forceinline__ void pla_window_queued(const DevTable& t, const LdsVi
                 const int pp = clamp_pos(pla_eval(v.knot[sg], v.c[sg], v.g[sg], x), t.m);
                 wb = (uint32_t)max(pp - e, 0) & ~3u;
             }
-            // the round's four steps of 16 addresses: every window load (and
-            // the boundary after each window, for the bracket check) is issued
-            // before any is used
-            uint32_t xx[4], bb[4], nx[4];
+            // the round's steps of 16 addresses (at most four; a step past the
+            // round's entries is skipped, wave-uniformly): every window load,
+            // and the boundary after each window for the bracket check, is
+            // issued before any is used
+            const uint32_t me = lane & 3u;
+            uint32_t xx[4], bb[4], c[4], nx = 0xFFFFFFFFu;
             uint4 w[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t src = 16u * k + (lane >> 2);
-                xx[k] = from_lane(src, x);
-                bb[k] = from_lane(src, wb);
+                xx[k] = 0u;
+                bb[k] = 0u;
+                if (16u * k < nr) {
+                    const uint32_t src = 16u * k + (lane >> 2);
+                    xx[k] = from_lane(src, x);
+                    bb[k] = from_lane(src, wb);
+                }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t src = 16u * k + (lane >> 2);
                 w[k] = make_uint4(0u, 0u, 0u, 0u);
-                nx[k] = 0xFFFFFFFFu;
-                if (src < nr) {  // quad-uniform
-                    w[k] = *reinterpret_cast<const uint4*>(t.B + bb[k] + 4u * (lane & 3u));
-                    if ((lane & 3u) == 0u) nx[k] = t.B[bb[k] + 16u];  // in the padding at worst
+                if (16u * k + (lane >> 2) < nr) {  // quad-uniform
+                    w[k] = *reinterpret_cast<const uint4*>(t.B + bb[k] + 4u * me);
+                    if (me == (uint32_t)k) nx = t.B[bb[k] + 16u];  // in the padding at worst
                 }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t src = 16u * k + (lane >> 2);
-                const uint32_t c = quad_sum((uint32_t)(w[k].x <= xx[k]) + (uint32_t)(w[k].y <= xx[k]) +
-                                            (uint32_t)(w[k].z <= xx[k]) + (uint32_t)(w[k].w <= xx[k]));
-                if (src < nr && (lane & 3u) == 0u) {
-                    bool ok = c >= 1u;
-                    if (c == 16u && bb[k] + 16u < t.m) ok = xx[k] < nx[k];
-                    uint32_t j = bb[k] + c - 1u;
-                    if (!ok) {
-                        atomicAdd(t.fallbacks, 1ull);
-                        j = upper_last(t.B, t.m, xx[k]);
-                    }
-                    j = min(j, t.m - 1);
-                    v.queue[r + src] = (v.member[j >> 5] >> (j & 31)) & 1u;
+                c[k] = 0u;
+                if (16u * k < nr)
+                    c[k] = quad_sum((uint32_t)(w[k].x <= xx[k]) + (uint32_t)(w[k].y <= xx[k]) +
+                                    (uint32_t)(w[k].z <= xx[k]) + (uint32_t)(w[k].w <= xx[k]));
+            }
+            // each lane finishes the step of its place in the quad: the bracket
+            // check, the interval's membership bit over the queue entry
+            const uint32_t cm = me == 0u ? c[0] : me == 1u ? c[1] : me == 2u ? c[2] : c[3];
+            const uint32_t xm = me == 0u ? xx[0] : me == 1u ? xx[1] : me == 2u ? xx[2] : xx[3];
+            const uint32_t bm = me == 0u ? bb[0] : me == 1u ? bb[1] : me == 2u ? bb[2] : bb[3];
+            const uint32_t src = 16u * me + (lane >> 2);
+            if (src < nr) {
+                bool ok = cm >= 1u;
+                if (cm == 16u && bm + 16u < t.m) ok = xm < nx;
+                uint32_t j = bm + cm - 1u;
+                if (!ok) {
+                    atomicAdd(t.fallbacks, 1ull);
+                    j = upper_last(t.B, t.m, xm);
                 }
+                j = min(j, t.m - 1);
+                v.queue[r + src] = (v.member[j >> 5] >> (j & 31)) & 1u;
             }
         }
         lds_wave_sync();
