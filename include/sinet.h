@@ -217,6 +217,13 @@ sinet_status sinet_table_create(const uint32_t* base, const uint8_t* len, const 
 sinet_status sinet_table_train(sinet_table* t, const sinet_train_params* params,
                                hipStream_t stream, sinet_train_report* report);
 
+/* The table's shape and its learned model's state (Algorithm 1's CIDR list
+ * as built by sinet_table_create: prefixes, interval boundaries m, device
+ * bytes, lookup kind and in/out index; for learned kinds the measured bound
+ * max_err, the PLA segments, whether the one-window search is used, and the
+ * number of fallbacks to the full search so far).  Errors: INVALID_ARG (t or
+ * out NULL), DEVICE (the fallback counter's read).  Synchronous: a blocking
+ * copy of the counter from the device. */
 sinet_status sinet_table_info(const sinet_table* t, sinet_table_info_t* out);
 
 /* Save the learned model of a trained table to HOST arrays: MLP: params[49];
@@ -273,16 +280,27 @@ sinet_status sinet_discriminate(const sinet_table* t, const uint32_t* src, const
 sinet_status sinet_label_runs(const uint8_t* label, uint64_t n, uint32_t* idx, uint64_t* totals,
                               hipStream_t stream);
 
-/* Histogram of already labelled sessions (map to (label, bin), reduce by
- * addition).  accumulate == 0: outputs are cleared first; 1: added to (the
- * paper's merge of per-chunk results).  Errors: INVALID_ARG for null
- * pointers, width_ms == 0, n_bins == 0. */
+/* Histogram of already labelled sessions: the sections "Map" (each session
+ * becomes the key (label, bin) with bin = (ts - t0) / width and the values
+ * (1, bytes)) and "Reduce" (values of equal keys added), with one exact
+ * counter per bin and label as in "Merge Scatter Pattern with CPU" (every
+ * 1-ms bin of the day).  Sessions before t0 or past the last bin are added to
+ * out->dropped.  accumulate == 0: outputs are cleared first; 1: added to (the
+ * merge of per-chunk results by addition of "Pairwise Reduction Pattern with
+ * GPU").  Columns, label and outputs are device memory of the caller.
+ * Errors: INVALID_ARG for null pointers, width_ms == 0, n_bins == 0.
+ * Asynchronous on stream. */
 sinet_status sinet_histogram(const uint32_t* ts, const uint64_t* bytes, const uint8_t* label,
                              uint64_t n, const sinet_window* win, sinet_hist* out,
                              int accumulate, hipStream_t stream);
 
-/* Discrimination fused with the histogram in one pass over the columns.
- * label may be NULL (not stored). */
+/* Discrimination (Algorithm 1, section "Threads for traffic direction
+ * discrimination with CIDR MATCH") fused with the histogram of
+ * sinet_histogram (sections "Map", "Reduce", "Merge Scatter Pattern with
+ * CPU") over one chunk of sessions: the paper's session pipeline of Fig. 2.
+ * label may be NULL (not stored); the other arguments and errors are those
+ * of sinet_discriminate and sinet_histogram.  The reduce is chosen by
+ * sinet_set_reduce.  Asynchronous on stream. */
 sinet_status sinet_pipeline(const sinet_table* t, const sinet_columns* cols,
                             const sinet_window* win, uint8_t* label, sinet_hist* out,
                             int accumulate, hipStream_t stream);
