@@ -273,7 +273,7 @@ sinet_status sinet_discriminate(const sinet_table* t, const uint32_t* src, const
  * label with a ballot per label and session slot and mbcnt, and takes its
  * class totals from popcounts; a count pass, a scan over the workgroups'
  * totals and a scatter pass place every index.  Caller-owned buffers; a workspace of 32 bytes per
- * 262,144 sessions comes from the stream-ordered pool.  Errors: INVALID_ARG
+ * 65,536 sessions comes from the stream-ordered pool.  Errors: INVALID_ARG
  * (totals NULL; label or idx NULL with n > 0), UNSUPPORTED (n >= 2^32: the
  * indices are 32-bit), OUT_OF_MEMORY.  n == 0 zeroes totals.  Asynchronous on
  * stream. */

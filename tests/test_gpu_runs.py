@@ -1,7 +1,7 @@
 """Label runs on the GPU (per-wave ballots and mbcnt ranks, class totals)
 against the oracle's stable partition, through the C ABI: every index and
-every total, bit for bit, over ragged sizes around the tile (16,384) and
-workgroup-range (262,144) sizes, unaligned label pointers, label bytes with
+every total, bit for bit, over ragged sizes around the tile (4,096) and
+workgroup-range (65,536) sizes and their multiples, unaligned label pointers, label bytes with
 high bits set, single-label inputs and the labels of a full-size day."""
 import sys
 
@@ -34,8 +34,9 @@ def _check(sinet, lab_host, lab_dev):
     assert np.array_equal(sinet.to_host_u32(idx), eidx)
 
 
-@pytest.mark.parametrize("n", [1, 3, 15, 16, 17, 4097, 16_383, 16_384, 16_385, 262_143, 262_144,
-                               262_145, 1_000_003, 9_000_001])
+@pytest.mark.parametrize("n", [1, 3, 15, 16, 17, 4095, 4096, 4097, 16_383, 16_384, 16_385,
+                               65_535, 65_536, 65_537, 262_143, 262_144, 262_145, 1_000_003,
+                               9_000_001])
 def test_random_labels_ragged(sinet, n):
     import torch
     _say("runs n", n)
