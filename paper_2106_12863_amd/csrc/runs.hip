@@ -44,7 +44,8 @@ constexpr uint32_t kNoLabel = 4u;                     // slots past the end matc
 // byte; sessions at or past n get kNoLabel.
 __device__ __forceinline__ uint4 run_labels16(const uint8_t* label, uint64_t i, uint64_t n, bool vec) {
     if (vec && i + kRunSlots <= n) {
-        const uint4 v = gload4(reinterpret_cast<const uint32_t*>(label + i));
+        // read once per pass: nontemporal
+        const u32x4_t v = __builtin_nontemporal_load(glob(reinterpret_cast<const u32x4_t*>(label + i)));
         return make_uint4(v.x & 0x03030303u, v.y & 0x03030303u, v.z & 0x03030303u, v.w & 0x03030303u);
     }
     uint32_t w[4] = {0u, 0u, 0u, 0u};
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(kRunLanes) k_runs_scatter(const uint8_t* __res
         const uint32_t d1 = run[1] - tb1, d2 = run[2] - tb2, d3 = run[3] - tb3;
         for (uint32_t q = threadIdx.x; q < valid; q += kRunLanes) {
             const uint32_t pos = q + (q < tb1 ? run[0] : q < tb2 ? d1 : q < tb3 ? d2 : d3);
-            *glob(idx + pos) = s_idx[q];
+            __builtin_nontemporal_store(s_idx[q], glob(idx + pos));  // written once
         }
 #pragma unroll
         for (uint32_t L = 0; L < 4; ++L) run[L] += tt[L];
