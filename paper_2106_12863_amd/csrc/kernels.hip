@@ -275,10 +275,11 @@ __device__ __forceinline__ uint32_t quad_sum(uint32_t x) {
 }
 
 // Membership bits of the addresses in cut /16 blocks by the window PLA, for a
-// wave whose 64 lanes are all active.  The window search's cost is the
-// memory pipeline's: unqueued, each address reads its 16-boundary window with
-// four 16-byte loads of its own lane, in waves where about a third of the
-// lanes need a search.  Here the addresses that need one, two slots at a time,
+// wave whose 64 lanes are all active.  Unqueued, each address reads its
+// 16-boundary window with four 16-byte loads of its own lane, in waves where
+// about a third of the lanes need a search, so a wave pays every slot's
+// segment search, window loads and compares whichever of its lanes need them.
+// Here the addresses that need one, two slots at a time,
 // are ranked with a ballot and mbcnt and queued in LDS; each round gives one
 // queued address to every lane, which finds its segment, evaluates the line
 // and forms the window's first index; then each quad of lanes takes one
