@@ -34,6 +34,7 @@ namespace sinet {
 
 constexpr uint32_t kRunLanes = 256;
 constexpr uint32_t kRunWaves = kRunLanes / 64;
+constexpr uint32_t kScanLanes = 1024;                 // the one scan workgroup
 constexpr uint32_t kRunSlots = 16;                    // consecutive sessions per lane in a tile
 constexpr uint32_t kRunTile = kRunSlots * kRunLanes;  // sessions per tile
 constexpr uint32_t kRunTiles = 16;                    // tiles per workgroup range
@@ -118,13 +119,13 @@ __global__ void __launch_bounds__(kRunLanes) k_runs_count(const uint8_t* __restr
 
 // Scan: run starts (label-major) plus each range's exclusive prefix, and the
 // totals.  One workgroup; lane j takes a contiguous slice of the ranges.
-__global__ void __launch_bounds__(kRunLanes) k_runs_scan(const uint32_t* __restrict__ cnt, uint32_t G,
+__global__ void __launch_bounds__(kScanLanes) k_runs_scan(const uint32_t* __restrict__ cnt, uint32_t G,
                                                          uint32_t* __restrict__ off,
                                                          unsigned long long* __restrict__ totals) {
-    __shared__ uint32_t s_p[4][kRunLanes];
+    __shared__ uint32_t s_p[4][kScanLanes];
     __shared__ uint32_t s_base[4];
     const uint32_t j = threadIdx.x;
-    const uint32_t per = (G + kRunLanes - 1) / kRunLanes;
+    const uint32_t per = (G + kScanLanes - 1) / kScanLanes;
     const uint32_t g0 = min(G, j * per), g1 = min(G, g0 + per);
     uint32_t loc[4] = {0u, 0u, 0u, 0u};
     for (uint32_t g = g0; g < g1; ++g)
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(kRunLanes) k_runs_scan(const uint32_t* __restr
     for (uint32_t L = 0; L < 4; ++L) s_p[L][j] = loc[L];
     __syncthreads();
     // inclusive scan of the slices, per label (Hillis-Steele over LDS)
-    for (uint32_t d = 1; d < kRunLanes; d <<= 1) {
+    for (uint32_t d = 1; d < kScanLanes; d <<= 1) {
         uint32_t v[4];
         for (uint32_t L = 0; L < 4; ++L) v[L] = j >= d ? s_p[L][j - d] : 0u;
         __syncthreads();
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(kRunLanes) k_runs_scan(const uint32_t* __restr
     if (j == 0) {
         uint32_t b = 0;
         for (uint32_t L = 0; L < 4; ++L) {
-            const uint32_t t = s_p[L][kRunLanes - 1];
+            const uint32_t t = s_p[L][kScanLanes - 1];
             s_base[L] = b;
             totals[L] = t;
             b += t;
@@ -259,7 +260,7 @@ extern "C" sinet_status sinet_label_runs(const uint8_t* label, uint64_t n, uint3
     hipLaunchKernelGGL(k_runs_count, dim3((uint32_t)G), dim3(kRunLanes), 0, stream, label, n, vec, cnt);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(kRunLanes), 0, stream, cnt, (uint32_t)G, off, tot);
+        hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(kScanLanes), 0, stream, cnt, (uint32_t)G, off, tot);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
