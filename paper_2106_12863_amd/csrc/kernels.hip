@@ -98,14 +98,23 @@ constexpr uint32_t kSearchQueue = 512;
 constexpr int kPlaGroup = 2;
 constexpr uint32_t kPlaQueue = 64u * kPlaGroup;
 
-// Kinds whose lookup pass queues its searches: the binary searches, the trie
-// and the MLP (measured faster with the queue: their searches are issue-bound),
-// and the window PLA, whose queued searches read each window with four lanes.
-// A PLA with a wider bound searches unqueued (the 256-segment PLA queued two
-// searches per lane was measured slower, 24.3 -> 37.5 ms per day).
+// Kinds whose lookup pass queues its searches: the binary searches, the trie,
+// the MLP and the PLA.  The window PLA reads each queued window with a quad of
+// lanes; the kinds whose search ends in a leaf of B in global memory (the
+// LDS-sampled binary search, the MLP, a PLA with a wider bound) read each
+// queued leaf with a quad of lanes, one round trip instead of a dependent
+// binary search (on the 1.6e9-session day: sampled binary search 18.9 -> 11.2
+// ms, MLP 23.2 -> 14.4 ms, 256-segment PLA 24.4 -> 13.2 ms; the same PLA queued
+// with its leaf binary searches was slower than unqueued, 24.3 -> 37.5 ms).
 __host__ __device__ constexpr bool queued_kind(uint32_t kind) {
     return kind == KK_BSEARCH || kind == KK_TRIE || kind == KK_MLP || kind == KK_PLA;
 }
+
+// Which queued searches a lookup instantiates (a template flag set): the
+// window PLA's, the others' (binary searches, trie, MLP, wider PLA), or both.
+constexpr int kQueueWindow = 1;
+constexpr int kQueueSearch = 2;
+constexpr int kQueueAll = kQueueWindow | kQueueSearch;
 
 // Orders this wave's LDS accesses: the ones before complete before the ones
 // after are issued (a wave's LDS requests are served in order; the clobber
@@ -157,14 +166,15 @@ __device__ __forceinline__ void leaf_search(const DevTable& t, const uint32_t* a
 // Learned forms: the model's rounded prediction p is within max_err = e of
 // the true interval j for every boundary key.  The leaf blocks that
 // [p - e, p + e] can touch are searched in the LDS copy of the sampled
-// boundaries (a window of uniform length, shifted inside the array), the
-// bracket top[b] <= a < top[b + 1] is confirmed, and the leaf is searched as in
-// the plain binary search.  A failed bracket (a wrong model or bound) falls
-// back to the full search and is counted, so results stay exact.
+// boundaries (a window of uniform length, shifted inside the array) and the
+// bracket top[b] <= a < top[b + 1] is confirmed, giving the leaf block b; the
+// leaf is then searched as in the plain binary search.  A failed bracket (a
+// wrong model or bound) falls back to the full search over the sample and is
+// counted, so results stay exact.
 template <int N>
-__device__ __forceinline__ void learned_search_n(const DevTable& t, const LdsView& v,
-                                                 const uint32_t* a, const int* p, uint32_t* j,
-                                                 uint32_t need) {
+__device__ __forceinline__ void learned_top_n(const DevTable& t, const LdsView& v,
+                                              const uint32_t* a, const int* p, uint32_t* j,
+                                              uint32_t need) {
     const uint32_t L = t.top_log2;
     const uint32_t nbl = min(((2 * t.max_err) >> L) + 2, t.n_top);
     uint32_t b[N], first[N];
@@ -196,6 +206,14 @@ __device__ __forceinline__ void learned_search_n(const DevTable& t, const LdsVie
         }
         j[q] = b[q];
     }
+}
+
+// The learned search: leaf block from the LDS sample, then the leaf.
+template <int N>
+__device__ __forceinline__ void learned_search_n(const DevTable& t, const LdsView& v,
+                                                 const uint32_t* a, const int* p, uint32_t* j,
+                                                 uint32_t need) {
+    learned_top_n<N>(t, v, a, p, j, need);
     leaf_search<N>(t, a, j, need);
 }
 
@@ -258,7 +276,8 @@ __device__ __forceinline__ uint32_t lane_id() {
 
 // Rank of this lane among the lanes set in m.
 __device__ __forceinline__ uint32_t rank_in(unsigned long long m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // x of lane src (every lane active).
@@ -379,6 +398,98 @@ __device__ __forceinline__ void pla_window_queued(const DevTable& t, const LdsVi
     }
 }
 
+// Leaf block of each address (the binary search over the LDS sample, or the
+// learned model and its bracket), for the kinds whose search ends in a leaf of
+// B in global memory.
+template <uint32_t KIND, int N>
+__device__ __forceinline__ void leaf_blocks(const DevTable& t, const LdsView& v, const uint32_t* a,
+                                            uint32_t* b, uint32_t need) {
+    if constexpr (KIND == KK_BSEARCH) {
+        upper_last_n<N>(v.top, t.n_top, a, b);
+    } else if constexpr (KIND == KK_MLP) {
+        int p[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            p[q] = (need >> q) & 1u ? clamp_pos(mlp_predict(v.w, t.m_f, a[q]), t.m) : 0;
+        learned_top_n<N>(t, v, a, p, b, need);
+    } else if constexpr (KIND == KK_PLA) {  // a PLA whose bound is too wide for one window
+        int p[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            p[q] = 0;
+            if (!((need >> q) & 1u)) continue;
+            const uint32_t r = a[q] >> (32 - t.radix_bits);
+            const uint32_t s0 = radix_entry(v.radix, r), s1 = radix_entry(v.radix, r + 1);
+            const uint32_t sg = s0 + upper_last(v.knot + s0, s1 - s0 + 1, a[q]);
+            p[q] = clamp_pos(pla_eval(v.knot[sg], v.c[sg], v.g[sg], a[q]), t.m);
+        }
+        learned_top_n<N>(t, v, a, p, b, need);
+    }
+}
+
+// Leaves read by quads of lanes: a wave whose 64 lanes are all active holds up
+// to 128 queued addresses x[h] (entry r + 64 h + lane) with their leaf blocks
+// b[h].  For each half, four steps of 16 addresses: a quad takes one address
+// per step (moved over with ds_bpermute), each of its lanes loads NL 16-byte
+// groups of the leaf's 16 NL boundaries and counts those <= the address, and
+// the quad adds its counts with DPP; every load of a half is issued before any
+// is used.  The interval is the leaf's first index plus the count minus one
+// (the leaf's first boundary is <= the address, as the sample said), exactly
+// what the leaf's binary search finds.  The lane at place k of a quad then
+// writes the membership bit of its quad's address of step k over the entry.
+template <int NL>
+__device__ __forceinline__ void leaf_quads(const DevTable& t, const LdsView& v, const uint32_t* x,
+                                           const uint32_t* b, uint32_t r, uint32_t nr,
+                                           uint32_t lane) {
+    const uint32_t me = lane & 3u, L = t.top_log2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (64u * h >= nr) break;  // wave-uniform
+        const uint32_t nh = min(nr - 64u * h, 64u);  // entries of this half
+        uint32_t xx[4], bb[4], c[4];
+        uint4 w[4][NL];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            xx[k] = 0u;
+            bb[k] = 0u;
+            if (16u * k < nh) {
+                const uint32_t src = 16u * k + (lane >> 2);
+                xx[k] = from_lane(src, x[h]);
+                bb[k] = from_lane(src, b[h]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int u = 0; u < NL; ++u) w[k][u] = make_uint4(0u, 0u, 0u, 0u);
+            if (16u * k + (lane >> 2) < nh) {  // quad-uniform
+                const uint4* leaf = reinterpret_cast<const uint4*>(t.B + (bb[k] << L));
+#pragma unroll
+                for (int u = 0; u < NL; ++u) w[k][u] = leaf[4 * u + me];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = 0u;
+            if (16u * k < nh) {
+                uint32_t n = 0;
+#pragma unroll
+                for (int u = 0; u < NL; ++u)
+                    n += (uint32_t)(w[k][u].x <= xx[k]) + (uint32_t)(w[k][u].y <= xx[k]) +
+                         (uint32_t)(w[k][u].z <= xx[k]) + (uint32_t)(w[k][u].w <= xx[k]);
+                c[k] = quad_sum(n);
+            }
+        }
+        const uint32_t cm = me == 0u ? c[0] : me == 1u ? c[1] : me == 2u ? c[2] : c[3];
+        const uint32_t bm = me == 0u ? bb[0] : me == 1u ? bb[1] : me == 2u ? bb[2] : bb[3];
+        const uint32_t src = 16u * me + (lane >> 2);
+        if (src < nh) {
+            const uint32_t j = min((bm << L) + cm - 1u, t.m - 1);
+            v.queue[r + 64u * h + src] = (v.member[j >> 5] >> (j & 31)) & 1u;
+        }
+    }
+}
+
 // Interval index of each address (all kinds but SCAN).  Addresses whose bit
 // in `need` is clear are skipped (their j is left unspecified); skipped lanes
 // issue no memory requests.
@@ -441,7 +552,7 @@ __device__ __forceinline__ uint32_t scan_owner(const DevTable& t, const LdsView&
 // address.  Label-only lookups first consult the /16 filter: a block that no
 // boundary cuts is entirely in or entirely out, which answers most addresses
 // from LDS; only addresses in cut blocks run the table's search.
-template <uint32_t KIND, int N, bool QUEUE = false>
+template <uint32_t KIND, int N, int QUEUE = 0>
 __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, const uint32_t* a,
                                         bool want_code, uint32_t* in, uint32_t* code) {
     if constexpr (KIND == KK_INOUT) {
@@ -465,7 +576,7 @@ __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, con
                 need |= (st[q] == 2u ? 1u : 0u) << q;
             }
         }
-        if constexpr (QUEUE && KIND == KK_PLA) {
+        if constexpr ((QUEUE & kQueueWindow) && KIND == KK_PLA) {
             if (v.queue && !want_code && t.filter_lds && t.pla_window && __ballot(1) == ~0ull) {
                 pla_window_queued<N>(t, v, a, need, in);
 #pragma unroll
@@ -476,52 +587,68 @@ __device__ __forceinline__ void lookups(const DevTable& t, const LdsView& v, con
                 return;
             }
         }
-        if (QUEUE && KIND != KK_PLA && v.queue && !want_code && t.filter_lds) {
-            // Wave-level compaction of the searches (section "Coordinated Batch
-            // Processing": the chunk is discriminated before the Map stage).  Only
-            // addresses in cut /16 blocks need one, about a third of them, yet a
-            // wave runs a slot's search whenever any of its lanes needs it.  The
-            // addresses that need one are ranked with a ballot and mbcnt per slot,
-            // queued in LDS, searched two per active lane per round (dense), and
-            // their membership bits read back from their queue entries.  Lanes may
-            // be inactive (the ragged last tile, the tail), so the active lanes are
-            // ranked among themselves.
-            const unsigned long long live = __ballot(1);
-            const uint32_t me = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u));
-            const uint32_t n_live = (uint32_t)__popcll(live);
-            uint32_t slot[N], cnt = 0;
+        if constexpr ((QUEUE & kQueueSearch) != 0) {
+            if (v.queue && !want_code && t.filter_lds && (KIND != KK_PLA || !t.pla_window)) {
+                // Wave-level compaction of the searches (section "Coordinated Batch
+                // Processing": the chunk is discriminated before the Map stage).  Only
+                // addresses in cut /16 blocks need one, about a third of them, yet a
+                // wave runs a slot's search whenever any of its lanes needs it.  The
+                // addresses that need one are ranked with a ballot and mbcnt per slot,
+                // queued in LDS, searched two per active lane per round (dense), and
+                // their membership bits read back from their queue entries.  Lanes may
+                // be inactive (the ragged last tile, the tail), so the active lanes are
+                // ranked among themselves.
+                const unsigned long long live = __ballot(1);
+                const uint32_t me = rank_in(live);
+                const uint32_t n_live = (uint32_t)__popcll(live);
+                uint32_t slot[N], cnt = 0;
 #pragma unroll
-            for (int q = 0; q < N; ++q) {
-                const bool nd = (need >> q) & 1u;
-                const unsigned long long m = __ballot(nd);
-                slot[q] = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (nd) v.queue[slot[q]] = a[q];
-                cnt += (uint32_t)__popcll(m);
-            }
-            if (cnt) {  // wave-uniform
-                lds_wave_sync();
-                for (uint32_t r = 0; r < cnt; r += 2 * n_live) {
-                    const uint32_t e0 = r + me, e1 = r + n_live + me;
-                    uint32_t x[2] = {e0 < cnt ? v.queue[e0] : 0u, e1 < cnt ? v.queue[e1] : 0u};
-                    uint32_t j[2] = {0u, 0u};
-                    intervals<KIND, 2>(t, v, x, j, (e0 < cnt ? 1u : 0u) | (e1 < cnt ? 2u : 0u));
-                    if (e0 < cnt) v.queue[e0] = (v.member[j[0] >> 5] >> (j[0] & 31)) & 1u;
-                    if (e1 < cnt) v.queue[e1] = (v.member[j[1] >> 5] >> (j[1] & 31)) & 1u;
+                for (int q = 0; q < N; ++q) {
+                    const bool nd = (need >> q) & 1u;
+                    const unsigned long long m = __ballot(nd);
+                    slot[q] = cnt + rank_in(m);
+                    if (nd) v.queue[slot[q]] = a[q];
+                    cnt += (uint32_t)__popcll(m);
                 }
-                lds_wave_sync();
+                if (cnt) {  // wave-uniform
+                    lds_wave_sync();
+                    // leaves of 16 or 32 boundaries in global memory, read by quads
+                    // of lanes when the whole wave is active
+                    const bool quads = KIND != KK_TRIE && n_live == 64u && t.n_top > 1 &&
+                                       (t.top_log2 == 4 || t.top_log2 == 5);
+                    if (quads) {
+                        for (uint32_t r = 0; r < cnt; r += 128) {
+                            const uint32_t nr = min(cnt - r, 128u);  // wave-uniform
+                            uint32_t x[2] = {me < nr ? v.queue[r + me] : 0u,
+                                             me + 64u < nr ? v.queue[r + 64u + me] : 0u};
+                            uint32_t b[2] = {0u, 0u};
+                            leaf_blocks<KIND, 2>(t, v, x, b,
+                                                 (me < nr ? 1u : 0u) | (me + 64u < nr ? 2u : 0u));
+                            if (t.top_log2 == 4) leaf_quads<1>(t, v, x, b, r, nr, me);
+                            else leaf_quads<2>(t, v, x, b, r, nr, me);
+                        }
+                    }
+                    for (uint32_t r = quads ? cnt : 0u; r < cnt; r += 2 * n_live) {
+                        const uint32_t e0 = r + me, e1 = r + n_live + me;
+                        uint32_t x[2] = {e0 < cnt ? v.queue[e0] : 0u, e1 < cnt ? v.queue[e1] : 0u};
+                        uint32_t j[2] = {0u, 0u};
+                        intervals<KIND, 2>(t, v, x, j, (e0 < cnt ? 1u : 0u) | (e1 < cnt ? 2u : 0u));
+                        if (e0 < cnt) v.queue[e0] = (v.member[j[0] >> 5] >> (j[0] & 31)) & 1u;
+                        if (e1 < cnt) v.queue[e1] = (v.member[j[1] >> 5] >> (j[1] & 31)) & 1u;
+                    }
+                    lds_wave_sync();
 #pragma unroll
-                for (int q = 0; q < N; ++q)
-                    if ((need >> q) & 1u) in[q] = v.queue[slot[q]];
-                lds_wave_sync();  // read back before the queue is written again
-            }
+                    for (int q = 0; q < N; ++q)
+                        if ((need >> q) & 1u) in[q] = v.queue[slot[q]];
+                    lds_wave_sync();  // read back before the queue is written again
+                }
 #pragma unroll
-            for (int q = 0; q < N; ++q) {
-                if (st[q] < 2u) in[q] = st[q];
-                code[q] = 0;
+                for (int q = 0; q < N; ++q) {
+                    if (st[q] < 2u) in[q] = st[q];
+                    code[q] = 0;
+                }
+                return;
             }
-            return;
         }
         if (need) {
             uint32_t j[N];
@@ -585,7 +712,7 @@ __device__ __forceinline__ uint4 gload4_nt(const uint32_t* q) {  // q 16-byte al
 }
 
 // Label of session i (scalar path); stores label / institutions when asked.
-template <uint32_t KIND, bool QUEUE = false>
+template <uint32_t KIND, int QUEUE = 0>
 __device__ __forceinline__ uint32_t label1(const PassParams& p, const LdsView& v, uint64_t i) {
     const uint32_t a[2] = {*glob(p.src + i), *glob(p.dst + i)};
     const bool wc = p.src_inst != nullptr || p.dst_inst != nullptr;
@@ -614,7 +741,7 @@ __device__ __forceinline__ void one_session(const PassParams& p, const LdsView& 
     if constexpr (KIND == KK_LABEL_IN) {
         lab = *glob(p.label_in + i) & 3u;
     } else {
-        lab = label1<KIND, HM == H_NONE && queued_kind(KIND)>(p, v, i);
+        lab = label1<KIND, HM == H_NONE && queued_kind(KIND) ? kQueueAll : 0>(p, v, i);
     }
     if constexpr (HM != H_NONE) account<HM>(p, h, lab, *glob(p.ts + i), *glob(p.bytes + i), d);
 }
@@ -622,7 +749,7 @@ __device__ __forceinline__ void one_session(const PassParams& p, const LdsView& 
 // Labels of four consecutive sessions starting at i from their loaded source
 // and destination words (or the given labels); stores labels / institutions
 // when asked.
-template <uint32_t KIND, bool QUEUE = false>
+template <uint32_t KIND, int QUEUE = 0>
 __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView& v, uint64_t i,
                                              uint4 s, uint4 t, uint32_t l4, uint32_t lab[4]) {
     if constexpr (KIND == KK_LABEL_IN) {
@@ -664,7 +791,7 @@ __device__ __forceinline__ void labels4_from(const PassParams& p, const LdsView&
     }
 }
 
-template <uint32_t KIND, bool QUEUE = false>
+template <uint32_t KIND, int QUEUE = 0>
 __device__ __forceinline__ void labels4(const PassParams& p, const LdsView& v, uint64_t i,
                                         uint32_t lab[4]) {
     uint4 s = make_uint4(0, 0, 0, 0), t = s;
@@ -692,7 +819,7 @@ __device__ __forceinline__ void four_sessions(const PassParams& p, const LdsView
         return;
     }
     uint32_t lab[4];
-    labels4<KIND, HM == H_NONE && queued_kind(KIND)>(p, v, i, lab);
+    labels4<KIND, HM == H_NONE && queued_kind(KIND) ? kQueueAll : 0>(p, v, i, lab);
     if constexpr (HM != H_NONE) {
         const uint4 ts = gload4(p.ts + i);
         const ulonglong2 b01 = gload2(p.bytes + i);
@@ -818,8 +945,8 @@ __device__ __forceinline__ void pass_body(const PassParams& p, const FarList& fa
                     const uint64_t g = tl * tile + threadIdx.x;
                     if (full(tl)) {
                         uint32_t lab[4];
-                        labels4_from<KIND, HM == H_NONE && queued_kind(KIND)>(p, v, g * 4, cs, cd,
-                                                                              0u, lab);
+                        constexpr int kQ = HM == H_NONE && queued_kind(KIND) ? kQueueAll : 0;
+                        labels4_from<KIND, kQ>(p, v, g * 4, cs, cd, 0u, lab);
                     } else if (g * 4 < p.n) {
                         for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
                             one_session<KIND, HM>(p, v, h, i, d);
@@ -1668,8 +1795,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_batch_lookup(BatchArgs a) {
             v = stage_lds<KIND>(s_bs.p.t, lds, &used);  // ends with a barrier
             // the window PLA's search queue, after the table (a.queue_words
             // per wave when the launch made room for it)
-            if constexpr (KIND == KK_PLA)
-                v.queue = a.queue_words ? lds + used + (tid >> 6) * a.queue_words : nullptr;
+            if constexpr (KIND == KK_PLA)  // window PLAs only (the wider search needs a larger queue)
+                v.queue = a.queue_words && s_bs.p.t.pla_window ? lds + used + (tid >> 6) * a.queue_words
+                                                               : nullptr;
             staged = si;
         }
         BatchStreamDev bs;
@@ -1698,7 +1826,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_batch_lookup(BatchArgs a) {
             }
             if (full(g)) {
                 uint32_t lab[4];
-                labels4_from<KIND, KIND == KK_PLA>(p, v, g * 4, cs, cd, 0u, lab);
+                labels4_from<KIND, KIND == KK_PLA ? kQueueWindow : 0>(p, v, g * 4, cs, cd, 0u, lab);
             } else {
                 Dropped d{};
                 for (uint64_t i = g * 4; i < p.n && i < g * 4 + 4; ++i)
@@ -2096,7 +2224,7 @@ static sinet_status launch_k_pass(const PassParams& p, uint32_t kind, int hm, bo
     // (the binary search over all boundaries in global memory, one leaf, is
     // latency-bound like the PLA and keeps the direct path)
     const bool global_search = kind == KK_BSEARCH && p.t.n_top <= 1;
-    const uint32_t qw = kind == KK_PLA ? (p.t.pla_window ? kPlaQueue : 0u) : kSearchQueue;
+    const uint32_t qw = kind == KK_PLA && p.t.pla_window ? kPlaQueue : kSearchQueue;
     if (hm == H_NONE && queued_kind(kind) && qw && !global_search && !p.pos_out && !p.src_inst &&
         !p.dst_inst && lds + (size_t)(block / 64) * qw * 4 <= 160 * 1024) {
         q.queue_words = qw;
