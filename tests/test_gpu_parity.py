@@ -519,8 +519,8 @@ def test_mlp_gradients_vs_oracle(sinet, torch):
 
 
 @pytest.mark.parametrize("kind,inout", [("pla", False), ("mlp", False), ("pla", True),
-                                        ("bsearch", False), ("bsearch_global", False),
-                                        ("trie", False)])
+                                        ("pla256", False), ("bsearch", False),
+                                        ("bsearch_global", False), ("trie", False)])
 def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, inout):
     """The 200,000-prefix clustered table: labels and histograms of every
     kind, with the kind's own search (in/out index off) and with the index."""
@@ -528,10 +528,10 @@ def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, in
     _say("large table", kind, inout)
     s = sinetgen.sessions(wl, start=0, stop=wl.n)
     ts, src, dst, nb = _up(sinet, s)
-    tab = sinet.Table(wl.pbase, wl.plen, kind=kind.replace("_global", ""), inout_index=inout,
-                      global_bsearch=kind.endswith("_global"))
+    tab = sinet.Table(wl.pbase, wl.plen, kind=kind.replace("_global", "").replace("256", ""),
+                      inout_index=inout, global_bsearch=kind.endswith("_global"))
     assert tab.info().inout_index == int(inout)
-    if kind not in ("pla", "mlp"):
+    if kind not in ("pla", "pla256", "mlp"):
         w = wl.window
         lab, out = sinet.pipeline(tab, ts, src, dst, nb, w.t0, w.width, w.n_bins)
         torch.cuda.synchronize()
@@ -540,7 +540,9 @@ def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, in
         assert np.array_equal(lab.cpu().numpy(), elab)
         _cmp_hist(sinet, out, (ec, eb, ed))
         return
-    rep = tab.train(steps=1500)
+    # the 256-segment PLA's bound is too wide for one window: its leaves are
+    # read by quads of lanes in the lookup pass's queue
+    rep = tab.train(segments=256) if kind == "pla256" else tab.train(steps=1500)
     info = tab.info()
     assert info.trained == 1 and info.max_err == rep.max_err
     if kind == "mlp":
@@ -557,6 +559,8 @@ def test_learned_lookup_exact_and_trained_beats_untrained(sinet, torch, kind, in
         assert tab.info().fallbacks == 0
         # the bound is small enough for one 16-boundary window per lookup
         assert tab.info().pla_window == 1 and tab.info().max_err <= 6
+    if kind == "pla256":
+        assert tab.info().fallbacks == 0 and tab.info().pla_window == 0 and tab.info().segments == 256
 
 
 def test_learned_forced_fallback_stays_exact(sinet, torch):
@@ -581,20 +585,23 @@ def test_learned_forced_fallback_stays_exact(sinet, torch):
         torch.cuda.synchronize()
         assert np.array_equal(sinet.to_host_u32(pos).astype(np.int64), learned.positions(B, q))
         assert tab.info().fallbacks > 0
+        # labels only, with the same wrong bound, at every boundary and the
+        # address below it, and a ragged tail of unqueued waves: the lookup
+        # pass's queued search (the PLA's window, or the MLP's leaf found
+        # through the full search over the sample), read by quads of lanes
+        tl = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=False)
         if kind == "pla":
-            # labels only: the lookup pass's queued window search (quads of
-            # lanes per window) with the same wrong bound, at every boundary
-            # and the address below it, and a ragged tail of unqueued waves
-            tl = sinet.Table(wl.pbase, wl.plen, kind=kind, inout_index=False)
             tl.set_model(pla=model, max_err=0)
             assert tl.info().pla_window == 1
-            src = np.concatenate([B, B - 1, q[:7]]).astype(np.uint32)
-            dst = rng.permutation(src)
-            lab, _, _ = sinet.discriminate(tl, sinet.to_device_u32(src), sinet.to_device_u32(dst))
-            torch.cuda.synchronize()
-            elab, _, _ = oracle.classify(wl.pbase, wl.plen, src, dst)
-            assert np.array_equal(lab.cpu().numpy(), elab)
-            assert tl.info().fallbacks > 0
+        else:
+            tl.set_model(params=model, max_err=0)
+        src = np.concatenate([B, B - 1, q[:7]]).astype(np.uint32)
+        dst = rng.permutation(src)
+        lab, _, _ = sinet.discriminate(tl, sinet.to_device_u32(src), sinet.to_device_u32(dst))
+        torch.cuda.synchronize()
+        elab, _, _ = oracle.classify(wl.pbase, wl.plen, src, dst)
+        assert np.array_equal(lab.cpu().numpy(), elab)
+        assert tl.info().fallbacks > 0
         # reloading with a measured bound restores exact, fallback-free PLA lookups
         if kind == "pla":
             tab2 = sinet.Table(wl.pbase, wl.plen, kind=kind)
