@@ -298,10 +298,10 @@ __device__ __forceinline__ uint32_t quad_sum(uint32_t x) {
 // 16-boundary window with four 16-byte loads of its own lane, in waves where
 // about a third of the lanes need a search, so a wave pays every slot's
 // segment search, window loads and compares whichever of its lanes need them.
-// Here the addresses that need one, two slots at a time,
-// are ranked with a ballot and mbcnt and queued in LDS; each round gives one
-// queued address to every lane, which finds its segment, evaluates the line
-// and forms the window's first index; then each quad of lanes takes one
+// Here the addresses that need one, two slots at a time, are ranked with a
+// ballot and mbcnt and queued in LDS; each round gives one queued address to
+// every lane, which finds its segment, evaluates the line and forms the
+// window's first index; then each quad of lanes takes one
 // address per step (its address and window start moved over with
 // ds_bpermute), each lane loads and compares four of the 16 boundaries, and
 // the quad's counts are added with DPP.  One load instruction covers 16
