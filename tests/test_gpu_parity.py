@@ -613,6 +613,37 @@ def test_learned_forced_fallback_stays_exact(sinet, torch):
             assert tab2.info().fallbacks == 0
 
 
+def test_leaf_sizes_of_a_larger_table(sinet, torch):
+    """150,000 random host routes (about 300,000 interval boundaries): the
+    sampled binary search keeps leaves of 32 boundaries in global memory (read
+    by quads of lanes, two 16-byte loads per lane), the learned kinds leaves of
+    64 (the queue's drain of two searches per lane).  Labels of 1,000,003
+    sessions, half of their endpoints on or next to a listed host, against
+    the oracle."""
+    rng = np.random.default_rng(31)
+    hosts = np.unique(rng.integers(0, 1 << 32, 150_000, dtype=np.uint64)).astype(np.uint32)
+    plen = np.full(hosts.shape[0], 32, np.uint8)
+    n = 1_000_003
+    near = rng.choice(hosts, n // 2) + rng.integers(0, 2, n // 2, dtype=np.uint32)
+    src = np.concatenate([near, rng.integers(0, 1 << 32, n - n // 2, dtype=np.uint64)]).astype(np.uint32)
+    dst = rng.permutation(src)
+    elab = oracle.classify(hosts, plen, src, dst, want_inst=False)
+    S, D = sinet.to_device_u32(src), sinet.to_device_u32(dst)
+    for kind in ("bsearch", "mlp", "pla"):
+        _say("larger table", kind)
+        tab = sinet.Table(hosts, plen, kind=kind, inout_index=False)
+        assert tab.info().m > 262_144
+        if kind == "mlp":
+            tab.train(steps=300)
+        elif kind == "pla":
+            tab.train(segments=256)
+        lab, _, _ = sinet.discriminate(tab, S, D)
+        torch.cuda.synchronize()
+        assert np.array_equal(lab.cpu().numpy(), elab), kind
+        if kind != "bsearch":
+            assert tab.info().fallbacks == 0, kind
+
+
 # ------------------------------------------------------------------ batching
 def _batch_setup(sinet, torch, n_streams=10, total=2_000_000, inout=True):
     import sinetgen.gpu as gg
