@@ -156,7 +156,7 @@ struct WinArgs {
                                     // step's slot on
     uint32_t* far_bits;             // [steps * kWinStep / 32] far-session bits of listed steps
     unsigned long long* events;     // [ev_cap] bin << 3 | label << 1 | wrap
-    unsigned long long* spill;      // [P][left, right][count, bytes][4][kWinBins]
+    uint32_t* spill;                // [P][left, right][4][kWinBins] ring words (count, byte sum)
     uint64_t ev_cap;
     uint32_t vec;                   // 16-byte column loads allowed
     int accumulate;

@@ -20,7 +20,8 @@
 //     writes every one of them (zeros included), so the histogram needs no
 //     zero-fill.  Its sessions that fall into the neighbours' bins (the time
 //     jitter around a boundary) are flushed into two spill rows of kWinBins
-//     bins, which a small fix-up pass adds into the neighbours' bins.
+//     bins (the packed ring words), which a small fix-up pass decodes and
+//     adds into the neighbours' bins.
 //   * Ring word.  count (5 bits) << 27 | byte sum (27 bits), one LDS atomic
 //     add of 2^27 + bytes per session; sessions with 2^22 bytes or more go
 //     to the far path, so the byte field cannot carry before the count field
@@ -138,8 +139,8 @@ struct WinPiece {
 
 // Write bins [lo, hi): those inside the window [W0, W0 + kWinBins) from the
 // ring (clearing their words), the rest as zeros; bins below Tq go to the
-// piece's left spill rows, bins from Tq1 on to its right spill rows, the
-// others to the output.  Wave w takes label w % 4 and the bins lo + 64 (w / 4)
+// piece's left spill rows, bins from Tq1 on to its right spill rows (the
+// packed ring word, 4 bytes per bin and label), the others to the output.  Wave w takes label w % 4 and the bins lo + 64 (w / 4)
 // + lane, + 256, ..., so the waves that have no bin return at once.  Called
 // by the whole workgroup with uniform arguments.  Accumulation is a template
 // parameter: a load here makes the wave wait for every load in flight, the
@@ -151,10 +152,10 @@ __device__ __forceinline__ void win_flush(const WinArgs& a, const WinPiece& g, u
     const uint64_t x0 = lo + 64ull * (wave >> 2);
     if (x0 >= hi) return;  // wave-uniform
     const uint32_t l = wave & 3u;
-    const uint64_t lrow = (((uint64_t)g.q * 2 + 0) * 2) * 4 + l;   // + 4 for byte sums
-    const uint64_t rrow = (((uint64_t)g.q * 2 + 1) * 2) * 4 + l;
-    unsigned long long* lc = a.spill + lrow * kWinBins + kWinBins - g.Tq;  // + x, x in [Tq - kWinBins, Tq)
-    unsigned long long* rc = a.spill + rrow * kWinBins - g.Tq1;            // + x, x in [Tq1, Tq1 + kWinBins)
+    const uint64_t lrow = ((uint64_t)g.q * 2 + 0) * 4 + l;
+    const uint64_t rrow = ((uint64_t)g.q * 2 + 1) * 4 + l;
+    uint32_t* lw = a.spill + lrow * kWinBins + kWinBins - g.Tq;  // + x, x in [Tq - kWinBins, Tq)
+    uint32_t* rw = a.spill + rrow * kWinBins - g.Tq1;            // + x, x in [Tq1, Tq1 + kWinBins)
     unsigned long long* oc = a.count + (uint64_t)l * a.n_bins;
     const uint64_t ob = (uint64_t)(a.hbytes - a.count);  // output byte row - count row
     const uint32_t trips = (uint32_t)((hi - x0 + 255) / 256);
@@ -169,18 +170,19 @@ __device__ __forceinline__ void win_flush(const WinArgs& a, const WinPiece& g, u
             w = ring[pos * 4 + l];
             ring[pos * 4 + l] = 0u;
         }
-        unsigned long long vc = w >> kCountShift, vb = w & kLowMask;
-        const bool own = x >= g.Tq && x < g.Tq1;
-        unsigned long long* dc = own ? oc + x : (x < g.Tq ? lc + x : rc + x);
-        unsigned long long* db = own ? dc + ob : dc + 4ull * kWinBins;
-        if constexpr (ACC) {
-            if (own) {
+        if (x >= g.Tq && x < g.Tq1) {  // owned: the bin's count and byte sum
+            unsigned long long vc = w >> kCountShift, vb = w & kLowMask;
+            unsigned long long* dc = oc + x;
+            unsigned long long* db = dc + ob;
+            if constexpr (ACC) {
                 vc += *glob(dc);
                 vb += *glob(db);
             }
+            __builtin_nontemporal_store(vc, glob(dc));
+            __builtin_nontemporal_store(vb, glob(db));
+        } else {  // a neighbour's: the ring word itself, decoded by the fix-up
+            __builtin_nontemporal_store(w, glob(x < g.Tq ? lw + x : rw + x));
         }
-        __builtin_nontemporal_store(vc, glob(dc));
-        __builtin_nontemporal_store(vb, glob(db));
     }
 }
 
@@ -519,22 +521,24 @@ __global__ void __launch_bounds__(1024) k_window_fixup(WinArgs a) {
     auto one = [&](uint32_t x) {
         const bool fa = x < ea, fb = x >= vb;
 #pragma unroll
-        for (uint32_t arr = 0; arr < 2; ++arr) {
-            unsigned long long* out = arr ? a.hbytes : a.count;
-#pragma unroll
-            for (uint32_t l = 0; l < 4; ++l) {
-                unsigned long long v = 0;
-                if (fa) {
-                    const uint64_t row = (((uint64_t)(q - 1) * 2 + 1) * 2 + arr) * 4 + l;
-                    v += *glob(a.spill + row * kWinBins + (x - Tq));
-                }
-                if (fb) {
-                    const uint64_t row = (((uint64_t)(q + 1) * 2 + 0) * 2 + arr) * 4 + l;
-                    v += *glob(a.spill + row * kWinBins + (x + kWinBins - Tq1));
-                }
-                unsigned long long* d = out + (uint64_t)l * a.n_bins + x;
-                *glob(d) = *glob(d) + v;
+        for (uint32_t l = 0; l < 4; ++l) {
+            unsigned long long vc = 0, vby = 0;  // the spilled ring words, decoded
+            if (fa) {
+                const uint64_t row = ((uint64_t)(q - 1) * 2 + 1) * 4 + l;
+                const uint32_t w = *glob(a.spill + row * kWinBins + (x - Tq));
+                vc += w >> kCountShift;
+                vby += w & kLowMask;
             }
+            if (fb) {
+                const uint64_t row = ((uint64_t)(q + 1) * 2 + 0) * 4 + l;
+                const uint32_t w = *glob(a.spill + row * kWinBins + (x + kWinBins - Tq1));
+                vc += w >> kCountShift;
+                vby += w & kLowMask;
+            }
+            unsigned long long* dc = a.count + (uint64_t)l * a.n_bins + x;
+            unsigned long long* db = a.hbytes + (uint64_t)l * a.n_bins + x;
+            *glob(dc) = *glob(dc) + vc;
+            *glob(db) = *glob(db) + vby;
         }
     };
     if (ea >= vb) {
@@ -613,7 +617,7 @@ size_t win_ws_bytes(uint64_t n, uint32_t P) {
     const uint64_t steps = (n + kWinStep - 1) / kWinStep;
     return al256w(4ull * (P + 1)) + 4 * al256w(4ull * P) + al256w(16) + al256w(4ull * steps) +
            al256w(4ull * kStepWords * steps) + al256w(8ull * win_event_cap(n)) +
-           al256w(8ull * P * 2 * 2 * 4 * kWinBins);
+           al256w(4ull * P * 2 * 4 * kWinBins);
 }
 
 WinArgs win_carve(void* base, const PassParams& p, uint32_t P, int accumulate) {
@@ -642,7 +646,7 @@ WinArgs win_carve(void* base, const PassParams& p, uint32_t P, int accumulate) {
     a.far_steps = (uint32_t*)take(4ull * steps);
     a.far_bits = (uint32_t*)take(4ull * kStepWords * steps);
     a.events = (unsigned long long*)take(8ull * win_event_cap(p.n));
-    a.spill = (unsigned long long*)take(8ull * P * 2 * 2 * 4 * kWinBins);
+    a.spill = (uint32_t*)take(4ull * P * 2 * 4 * kWinBins);
     a.ev_cap = win_event_cap(p.n);
     a.pieces = P;
     a.vec = ((((uintptr_t)p.ts | (uintptr_t)p.bytes) & 15u) == 0 && ((uintptr_t)p.label_in & 3u) == 0)
