@@ -59,7 +59,7 @@ DEFAULT_FORMS = "plain,bsearch,bsearch_lds,trie,pla,pla256,mlp,batched_inout,bat
 COUNTER_TRAFFIC = {
     "k_window": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms",
                  "sources": ("window.hip", "pass_common.h", "sinet_internal.h"),
-                 "kernels_sha": "4c3695f983cd2a45", "bytes": 26.754e9},
+                 "kernels_sha": "aa00b7ba0d8d2428", "bytes": 26.632e9},
     "k_stage1": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "7b136c4cdca9f0c5",
                  "bytes": 40.32e9},
     "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "7b136c4cdca9f0c5",
