@@ -652,7 +652,7 @@ def bench_host(args, torch, sinet, sinetgen, gg):
         "roofline": {"bound": "host link", "achieved": achieved, "peak": h2d, "unit": "GB/s",
                      "frac": achieved / h2d, "traffic": None,
                      "kernel": "host-to-device copies of the columns (labels back concurrently)",
-                     "peak_note": "measured pinned host-to-device copy rate on this box"},
+                     "peak_note": "measured pinned host-to-device copy rate of this machine"},
         "forms": {"pinned": {"ms_per_step": ms_pin, "sessions_per_s": wl.n / (ms_pin * 1e-3)},
                   "pageable": {"ms_per_step": ms_page,
                                "sessions_per_s": wl.n / (ms_page * 1e-3)}},
