@@ -60,6 +60,7 @@ constexpr int kMaxBlock = 1024;
 constexpr int kStage2Block = 512;
 constexpr int kSegMax = 256;               // segment descriptors of a block held in LDS
 constexpr int kRecUnroll = 8;              // independent record loads per stage-2 lane
+constexpr uint32_t kStage2Run = 16;         // consecutive stage-2 blocks per XCD turn
 constexpr uint32_t kSmallMax = 1u << 19;  // byte counts stored inline in a record
 constexpr uint64_t kMaxPiece = 1ull << 31;  // sessions per partitioned pass (32-bit slots)
 
@@ -1311,7 +1312,7 @@ __global__ void k_fill(PartWs w) {
     }
 }
 
-// Stage 2.  Persistent workgroups take the blocks of their XCD's range in turn (stage2_run).
+// Stage 2.  Persistent workgroups take their XCD's blocks in turn (stage2_run).
 // A block's segment descriptors (first slot, 16-byte groups) sit in LDS,
 // double-buffered: while a block's records are accumulated, the next block's
 // descriptors and the segment range of the one after it are in flight.
@@ -1480,24 +1481,32 @@ __device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t
     }
 }
 
-// The persistent block loop; out(g) names where block g's bins go.  Each XCD
-// (workgroup w runs on XCD w % kXcds) takes a contiguous range of blocks, its
-// S workgroups blocks lo + lid, + S, ...: neighbouring blocks are written at
-// about the same time through the same L2, so a 128-byte line that two blocks
-// share (rows whose length is not a multiple of 16 bins) is completed there
-// rather than written to HBM in two parts.  On 64 uneven streams the batch's
-// stage 2 took 5.48 ms this way against 5.70 ms with blocks dealt round-robin.
+// The persistent block loop; out(g) names where block g's bins go.  Runs of
+// kStage2Run consecutive blocks are dealt round-robin over the XCDs (workgroup
+// w runs on XCD w % kXcds), and an XCD's S workgroups take its blocks in
+// turn: neighbouring blocks are written at about the same time through the
+// same L2, so a 128-byte line that two blocks share (rows whose length is not
+// a multiple of 16 bins) is completed there rather than written to HBM in two
+// parts, while every XCD still gets a share of every part of the histogram.
+// On 64 uneven streams the batch's stage 2 took 5.33-5.35 ms this way, 5.68-
+// 5.72 ms with blocks dealt round-robin one at a time and 5.47-5.48 ms with one
+// contiguous range per XCD (which also slowed the day cut into 24 hourly
+// streams, whose busy hours then fell on a few XCDs: 11.33 -> up to 11.83 ms).
 template <class Out>
 __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, const Out& out) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t G = gridDim.x;
+    const uint32_t G = gridDim.x, nb = w.n_blocks;
+    const uint32_t X = G < (uint32_t)kXcds ? G : (uint32_t)kXcds;  // XCDs with workgroups
     const uint32_t xcd = blockIdx.x % kXcds, lid = blockIdx.x / kXcds;
     const uint32_t per = G / kXcds, rem = G % kXcds;
     const uint32_t S = per + (xcd < rem ? 1u : 0u);  // workgroups on this XCD
-    const uint64_t cum = (uint64_t)xcd * per + min(xcd, rem);
-    // this XCD's blocks: [n_blocks * cum / G, nb)
-    const uint32_t nb = (uint32_t)((uint64_t)w.n_blocks * (cum + S) / G);
-    uint32_t g = (uint32_t)((uint64_t)w.n_blocks * cum / G) + lid;
+    // the XCD's t-th block (increasing in t; nb once past the last block)
+    auto blk = [&](uint32_t t) -> uint32_t {
+        const uint64_t b = ((uint64_t)(t / kStage2Run) * X + xcd) * kStage2Run + t % kStage2Run;
+        return b < nb ? (uint32_t)b : nb;
+    };
+    uint32_t t = lid;
+    uint32_t g = blk(t);
     if (g >= nb) return;
     for (uint32_t k = tid; k < 4 * kBlockBins; k += kStage2Block) {
         sh.b[k] = 0;
@@ -1511,21 +1520,21 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
             sh.s1[0] = s1;
         }
     }
-    uint32_t gn = g + S;  // next block, and its segment range
+    uint32_t gn = blk(t + S);  // next block, and its segment range
     uint32_t n0 = 0, n1 = 0;
     if (gn < nb) {
         n0 = w.seg_off[gn];
         n1 = w.seg_off[gn + 1];
     }
     BlockOut cur = out(g);  // where the current block's bins go (found one block ahead)
-    for (uint32_t d = 0; g < nb; g = gn, gn += S, d ^= 1u) {
+    for (uint32_t d = 0; g < nb; t += S, g = gn, gn = blk(t + S), d ^= 1u) {
         __syncthreads();  // descriptors of g in buffer d, accumulators clear
         // in flight during this block: the next block's descriptors and the
         // segment range of the block after it
         const uint32_t nn = gn < nb ? min(n1 - n0, (uint32_t)kSegMax) : 0u;
         uint2 nsg = make_uint2(0u, 0u);
         if (tid < nn) nsg = w.segs[n0 + tid];
-        const uint32_t gnn = gn + S;
+        const uint32_t gnn = blk(t + 2 * S);
         uint32_t m0 = 0, m1 = 0;
         if (gnn < nb) {
             m0 = w.seg_off[gnn];
