@@ -65,13 +65,13 @@ COUNTER_TRAFFIC = {
     "k_stage2": {"workload": "fullday-1.6e9-200kpfx-86.4M1ms", "kernels_sha": "7b136c4cdca9f0c5",
                  "bytes": 12.98e9},
     "k_watch": {"workload": "watch-fullday-1.6e+09-1177hosts-144x10min",
-                "kernels_sha": "d5bb2ef722bcabf1", "bytes": 14.77e9},
+                "kernels_sha": "99b1e3a42fb8af19", "bytes": 14.77e9},
     "k_rebin_tiles": {"workload": "rebin-4x86.4M1ms-to-24x1h", "sources": ("rebin.hip", "sinet_internal.h"),
                       "kernels_sha": "c72070d268c5ab90", "bytes": 2.766e9},
     # the eight kernels of one batch graph launch together (the last launch of the run)
     "batch_graph": {"workload": "batch-64streams-299999969sessions",
                     "sources": ('batch.hip', 'kernels.hip', 'sinet_internal.h', 'sinet_device.h', 'inout_index.h'),
-                    "kernels_sha": "85387adfaea9306d", "bytes": 28.05e9},
+                    "kernels_sha": "7ec2adec32cac174", "bytes": 28.05e9},
     # the four kernels of one parse call together, summed the same way
     "parse_call": {"workload": "parse-4.0GB-20000000lines", "sources": ("parse.hip", "sinet_internal.h"),
                    "kernels_sha": "2a306051f3f37ac9", "bytes": 12.69e9},

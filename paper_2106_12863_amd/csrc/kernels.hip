@@ -60,7 +60,7 @@ constexpr int kMaxBlock = 1024;
 constexpr int kStage2Block = 512;
 constexpr int kSegMax = 256;               // segment descriptors of a block held in LDS
 constexpr int kRecUnroll = 8;              // independent record loads per stage-2 lane
-constexpr uint32_t kStage2Run = 16;         // consecutive stage-2 blocks per XCD turn
+constexpr uint32_t kStage2Run = 16;         // consecutive stage-2 blocks per XCD turn (rows off a line)
 constexpr uint32_t kSmallMax = 1u << 19;  // byte counts stored inline in a record
 constexpr uint64_t kMaxPiece = 1ull << 31;  // sessions per partitioned pass (32-bit slots)
 
@@ -1482,18 +1482,21 @@ __device__ __forceinline__ void stage2_write(Stage2Shared& sh, const BlockOut& t
 }
 
 // The persistent block loop; out(g) names where block g's bins go.  Runs of
-// kStage2Run consecutive blocks are dealt round-robin over the XCDs (workgroup
-// w runs on XCD w % kXcds), and an XCD's S workgroups take its blocks in
-// turn: neighbouring blocks are written at about the same time through the
-// same L2, so a 128-byte line that two blocks share (rows whose length is not
-// a multiple of 16 bins) is completed there rather than written to HBM in two
-// parts, while every XCD still gets a share of every part of the histogram.
-// On 64 uneven streams the batch's stage 2 took 5.33-5.35 ms this way, 5.68-
-// 5.72 ms with blocks dealt round-robin one at a time and 5.47-5.48 ms with one
-// contiguous range per XCD (which also slowed the day cut into 24 hourly
-// streams, whose busy hours then fell on a few XCDs: 11.33 -> up to 11.83 ms).
+// `run` consecutive blocks are dealt round-robin over the XCDs (workgroup w
+// runs on XCD w % kXcds), and an XCD's S workgroups take its blocks in turn.
+// With runs of kStage2Run, neighbouring blocks are written at about the same
+// time through the same L2, so a 128-byte line that two blocks share (rows
+// whose length is not a multiple of 16 bins) is completed there rather than
+// written to HBM in two parts, while every XCD still gets a share of every
+// part of the histogram.  On 64 uneven streams the batch's stage 2 took
+// 5.33-5.35 ms this way, 5.68-5.72 ms with runs of one block and 5.47-5.48 ms
+// with one contiguous range per XCD (which also slowed the day cut into 24
+// hourly streams, whose busy hours then fell on a few XCDs: 11.33 -> up to
+// 11.83 ms).  Where every row starts on a line, runs of one block are faster
+// (the 1e8-session day: 1.19 against 1.23 ms).
 template <class Out>
-__device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, const Out& out) {
+__device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, const Out& out,
+                                           uint32_t run) {
     const uint32_t tid = threadIdx.x;
     const uint32_t G = gridDim.x, nb = w.n_blocks;
     const uint32_t X = G < (uint32_t)kXcds ? G : (uint32_t)kXcds;  // XCDs with workgroups
@@ -1502,7 +1505,7 @@ __device__ __forceinline__ void stage2_run(const PartWs& w, Stage2Shared& sh, co
     const uint32_t S = per + (xcd < rem ? 1u : 0u);  // workgroups on this XCD
     // the XCD's t-th block (increasing in t; nb once past the last block)
     auto blk = [&](uint32_t t) -> uint32_t {
-        const uint64_t b = ((uint64_t)(t / kStage2Run) * X + xcd) * kStage2Run + t % kStage2Run;
+        const uint64_t b = ((uint64_t)(t / run) * X + xcd) * run + t % run;
         return b < nb ? (uint32_t)b : nb;
     };
     uint32_t t = lid;
@@ -1585,7 +1588,8 @@ __global__ void __launch_bounds__(kStage2Block) k_stage2(PartWs w, unsigned long
                                                         unsigned long long* hbytes, uint32_t n_bins,
                                                         int accumulate) {
     __shared__ Stage2Shared sh;
-    stage2_run(w, sh, PlainOut{count, hbytes, n_bins, accumulate});
+    const bool lines = (n_bins & 15u) == 0 && (((uintptr_t)count | (uintptr_t)hbytes) & 127u) == 0;
+    stage2_run(w, sh, PlainOut{count, hbytes, n_bins, accumulate}, lines ? 1u : kStage2Run);
 }
 
 __global__ void k_zero(unsigned long long* __restrict__ p, uint64_t n) {
@@ -1728,7 +1732,7 @@ struct BatchOut {
 
 __global__ void __launch_bounds__(kStage2Block) k_batch_stage2(BatchArgs a, PartWs w) {
     __shared__ Stage2Shared sh;
-    stage2_run(w, sh, BatchOut{&a});
+    stage2_run(w, sh, BatchOut{&a}, kStage2Run);
 }
 
 
